@@ -1,0 +1,214 @@
+"""Benchmark of the sliced stem contraction on one MI355X.
+
+Workload (default): the 5x6-grid, 14-cycle random circuit (30 qubits) with
+6 open qubits (a 64-amplitude batch) and 10 sliced labels, i.e. 2^10
+slices; one *step* is one pass of the whole hot path over that batch --
+every slice contracted (stem permutes + complex products on the matrix
+cores) and summed in FP64 into the 64 amplitudes.  The plan is made before
+the timed region (preprocessing is not timed, as in the paper).
+
+Prints one JSON line: TFLOP/s (8 real flops per complex multiply-add,
+summed over the steps' useful products) and slices/s for the FP32 path,
+the same for the split-FP16 path, the amplitude error of both against the
+FP64 oracle on sampled slices, a roofline entry for the dominant kernel
+(the FP32 product, HBM-bound) and the oracle's own rate on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_net():
+    from paper_2005_06787_amd import planner
+    from workloads import configs, tensors
+    from workloads.circuits import make_circuit
+
+    cfg = configs.CIRCUIT_CONFIGS["c2_5x6_m14"]
+    circ = make_circuit(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"])
+    oq = configs.open_qubits(cfg)
+    pre = tensors.split_open_prefix(circ["n_qubits"], oq, cfg["prefix_seed"])
+    closed = dict(zip(pre["closed"], pre["closed_bits"]))
+    net = planner.plan_circuit(circ, oq, closed, n_sliced=cfg["n_sliced"], trials=64, seed=0)
+    return net, cfg
+
+
+def timed_run(plan, steps, warmup, n_slices, stream):
+    import torch
+
+    out = torch.empty((1, 1 << plan.n_open), dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        plan.contract(0, n_slices, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        # per-kernel hipEvents on the last slice of the last step only
+        plan.contract(0, n_slices, out=out, stream=stream, time_steps=(k == steps - 1))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, out
+
+
+def roofline(plan):
+    steps = plan.steps()
+    g_bytes = sum(s["bytes"] for s in steps)
+    g_us = sum(s["last_gemm_us"] for s in steps)
+    p_bytes = sum(s["perm_bytes"] for s in steps)
+    p_us = sum(s["last_perm_us"] for s in steps if s["permuted"])
+    launches = len(steps)
+    achieved = g_bytes / (g_us * 1e-6) / 1e9
+    return {
+        "kernel": "stem_cgemm_f32_kernel",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "bytes_per_launch": g_bytes / launches,
+        "avg_launch_us": g_us / launches,
+        "permute": {"achieved": round(p_bytes / (p_us * 1e-6) / 1e9, 1) if p_us > 0 else None,
+                    "bytes_per_slice": p_bytes, "us_per_slice": p_us},
+    }
+
+
+def cpu_baseline(net, sample_slices, flops_per_slice):
+    """The FP64 oracle, as it stands, on a few slices (host cores)."""
+    from oracle import stemnet
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    onet = dict(net)
+    onet["stem"] = {"labels": net["stem"]["labels"],
+                    "data": np.asarray(net["stem"]["data"], np.complex128)}
+    onet["branches"] = [{"labels": b["labels"], "data": np.asarray(b["data"], np.complex128)}
+                        for b in net["branches"]]
+    refs = {}
+    t0 = time.perf_counter()
+    for s in sample_slices:
+        v, _ = stemnet.run_slice(onet, int(s))
+        refs[int(s)] = v.reshape(-1)
+    dt = time.perf_counter() - t0
+    rate = len(sample_slices) / dt
+    return {"value": round(rate * flops_per_slice / 1e12, 6), "unit": "TFLOP/s",
+            "slices_per_s": round(rate, 4), "cores": int(cores), "kind": "oracle",
+            "sample": f"{len(sample_slices)} slices of the 2^10 (FP64 plan-following "
+                      f"contraction, {dt:.1f} s)"}, refs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-FP16 run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "layout is a design, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from oracle import stats
+    from paper_2005_06787_amd import Plan
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    net, cfg = make_net()
+    log(f"plan made in {time.perf_counter() - t0:.1f} s: {net['stats']}")
+    stream = torch.cuda.current_stream()
+
+    results = {}
+    plans = {}
+    for precision in (["fp32"] if args.no_split else ["fp32", "split_fp16"]):
+        plan = Plan(net, precision=precision)
+        summ = plan.summary()
+        n_slices = summ["n_slices"]
+        dt, out = timed_run(plan, args.steps, args.warmup, n_slices, stream)
+        ms = dt / args.steps * 1e3
+        flops = summ["flops_per_slice"] * n_slices
+        results[precision] = {
+            "ms_per_step": ms,
+            "tflops": flops / (ms * 1e-3) / 1e12,
+            "slices_per_s": n_slices / (ms * 1e-3),
+            "amps": out.cpu().numpy()[0],
+            "summary": summ,
+        }
+        plans[precision] = plan
+        log(f"{precision}: {ms:.2f} ms per step ({n_slices} slices), "
+            f"{results[precision]['tflops']:.3f} TFLOP/s, "
+            f"{results[precision]['slices_per_s']:.1f} slices/s")
+
+    fp32 = results["fp32"]
+    summ = fp32["summary"]
+    line = {
+        "metric": "stem contraction TFLOP/s & slices/s, split-FP16 vs FP32, at 1e-5 amp error",
+        "value": round(fp32["tflops"], 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fp32["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "5x6 grid, 14 cycles, 30 qubits, 6 open (64 amplitudes), "
+                               "2^10 slices, FP32 complex products",
+                   "n_slices": summ["n_slices"], "n_steps": summ["n_steps"],
+                   "peak_rank": summ["peak_rank"], "n_permutes": summ["n_permutes"],
+                   "parallelism": "1 GPU"},
+        "slices_per_s": round(fp32["slices_per_s"], 2),
+        "flops_per_slice": summ["flops_per_slice"],
+        "bytes_per_slice": summ["bytes_per_slice"],
+        "roofline": roofline(plans["fp32"]),
+    }
+    if "split_fp16" in results:
+        sp = results["split_fp16"]
+        line["split_fp16"] = {"value": round(sp["tflops"], 4), "unit": "TFLOP/s",
+                              "slices_per_s": round(sp["slices_per_s"], 2),
+                              "ms_per_step": round(sp["ms_per_step"], 3)}
+    # amplitude error: sampled slices against the FP64 oracle (also the CPU baseline)
+    if not args.no_cpu:
+        rng = np.random.Generator(np.random.PCG64(cfg["slice_sample_seed"]))
+        sample = [int(s) for s in rng.choice(summ["n_slices"], size=16, replace=False)]
+        base, refs = cpu_baseline(net, sample, summ["flops_per_slice"])
+        line["cpu_baseline"] = base
+        errs = {}
+        for precision, plan in plans.items():
+            worst = 0.0
+            for s in sample[:4]:
+                got = plan.contract(s, s + 1).cpu().numpy()[0]
+                worst = max(worst, stats.rel_l2(got, refs[s]))
+            errs[precision] = worst
+        line["amp_rel_l2_vs_oracle"] = errs
+    print(json.dumps(line), flush=True)
+    for p in plans.values():
+        p.close()
+
+
+if __name__ == "__main__":
+    main()

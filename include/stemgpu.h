@@ -1,0 +1,198 @@
+/*
+ * stemgpu: contraction of a sliced stem network on one MI355X (gfx950).
+ *
+ * The method (paper §3, §4, §A.1-§A.3): a tensor network whose every bond has
+ * dimension 2 is contracted along a "stem", one large tensor that absorbs
+ * small pre-computed branch tensors one after another (§A.2 stems and
+ * branches, §A.3 branch pre-computation).  A set of "sliced" labels E_s is
+ * enumerated outside the contraction: each assignment of E_s (a slice)
+ * selects a sub-network, and the value of the whole network is the sum of
+ * the sub-network values over all slices (§A.1, slicing; the scheme
+ * (E_s, T)).  A batch of amplitudes is obtained by leaving some output
+ * labels open and fixing the others ("projected" labels, §3: a batch of
+ * amplitudes whose closed qubits share one assignment).
+ *
+ * Every function returns a stem_status (0 = success).  No C++ exception
+ * crosses this interface.  On failure stem_last_error() returns a message
+ * (thread-local; valid until the next call on the same thread).
+ *
+ * Memory conventions.  A complex number is two consecutive values (real,
+ * imaginary).  A tensor of rank r over a label list L is stored as 2^r
+ * complex numbers in C order: label L[0] is the most significant bit of
+ * the entry index.  "Device" pointers are HIP device allocations on the
+ * current device; "host" pointers are ordinary host memory.  A stream
+ * argument is a hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef STEMGPU_H
+#define STEMGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t stem_status;
+
+enum {
+  STEM_OK = 0,
+  STEM_EINVAL = 1,        /* null pointer, negative size, inconsistent descriptor */
+  STEM_ELABEL = 2,        /* a label occurs in a number of tensors the method does not allow */
+  STEM_ESHAPE = 3,        /* a rank exceeds the plan's limit */
+  STEM_EUNSUPPORTED = 4,  /* a valid network the library does not handle yet */
+  STEM_ENOMEM = 5,        /* workspace too small, or a device allocation failed */
+  STEM_ERANGE = 6,        /* slice range or projected assignment out of range */
+  STEM_EHIP = 7           /* a HIP runtime call failed; the message names it */
+};
+
+/* Arithmetic of the complex matrix products of the stem steps. */
+enum {
+  STEM_FP32 = 0,          /* FP32 inputs, FP32 MFMA products, FP32 accumulation */
+  STEM_SPLIT_FP16 = 1,    /* three-term FP16 split of both factors, FP32 accumulation */
+  STEM_SPLIT_BF16 = 2     /* three-term BF16 split of both factors, FP32 accumulation */
+};
+
+/* Flags of stem_contract. */
+enum {
+  STEM_ACCUMULATE = 1,    /* add the range's sum to out instead of overwriting it */
+  STEM_TIME_STEPS = 2     /* time every kernel of the range's last slice (hipEvents);
+                             read back with stem_step_info after the stream syncs */
+};
+
+/*
+ * A sliced stem network (paper §A.1: the slicing scheme (E_s, T) restricted
+ * to a stem-shaped tree T, §A.2).  Labels are arbitrary non-negative int32
+ * values; every bond has dimension 2 (§A.1).
+ *
+ * Label rules checked by stem_plan_validate / stem_plan_create:
+ *  - an open label occurs in exactly one tensor;
+ *  - a sliced or projected label occurs in at least one tensor and is not open;
+ *  - every other label occurs in exactly two tensors;
+ *  - a label the stem shares with branch i occurs in no later branch
+ *    (otherwise it would be a hyperedge: STEM_EUNSUPPORTED);
+ *  - after the last branch the stem carries exactly the open labels.
+ * Step i contracts the stem with branch i over the labels they share (after
+ * the sliced and projected labels are fixed), which is one pairwise
+ * contraction of §A.1 with time 2^|E_AB| and space 2^|E*_AB|.
+ */
+typedef struct stem_plan_desc {
+  int32_t n_open;
+  const int32_t* open_labels;     /* host; result index order, first = most significant */
+  int32_t n_sliced;
+  const int32_t* sliced_labels;   /* host; slice id bit (n_sliced-1-j) is the value of label j */
+  int32_t n_proj;
+  const int32_t* proj_labels;     /* host; projected assignment bit (n_proj-1-j) = label j */
+  int32_t stem_rank;
+  const int32_t* stem_labels;     /* host; labels of the initial stem, C order */
+  const float* stem_data;         /* 2^stem_rank complex64, host or device (below) */
+  int32_t stem_on_device;         /* nonzero: stem_data is a device pointer */
+  int32_t n_branches;
+  const int32_t* branch_ranks;    /* host; [n_branches] */
+  const int32_t* branch_labels;   /* host; every branch's labels, concatenated */
+  const float* branch_data;       /* host; every branch's 2^rank complex64, concatenated */
+  int32_t precision;              /* STEM_FP32, STEM_SPLIT_FP16 or STEM_SPLIT_BF16 */
+  int32_t max_rank;               /* largest allowed stem rank; 0 = 33 */
+} stem_plan_desc;
+
+/* Shape and cost of one stem step (paper §A.1: time 2^|E_AB| complex
+ * multiply-adds; one complex multiply-add = 8 real floating-point ops). */
+typedef struct stem_step_info {
+  int32_t rank_in;        /* stem rank before the step (sliced/projected labels removed) */
+  int32_t rank_out;       /* stem rank after the step */
+  int32_t n_shared;       /* s: labels summed in this step, K = 2^s */
+  int32_t n_free;         /* f: new labels from the branch, N = 2^f */
+  int32_t permuted;       /* 1 if a stem permute runs before the product */
+  int32_t reserved;
+  int64_t M, K, N;        /* product [M x K] . [K x N] -> [M x N], complex */
+  double flops;           /* 8 M K N */
+  double bytes;           /* 8 (M K + M N + K N): one read of stem and branch, one write */
+  double perm_bytes;      /* 16 * 2^rank_in if permuted, else 0 */
+  float last_gemm_us;     /* from the last STEM_TIME_STEPS call, or -1 */
+  float last_perm_us;     /* idem for the permute, or -1 */
+} stem_step_info;
+
+/* Summary of a plan, computed on the host without a GPU. */
+typedef struct stem_plan_summary {
+  int32_t n_steps;
+  int32_t peak_rank;      /* largest stem rank over the steps, initial stem included */
+  int32_t n_permutes;     /* steps that need a stem permute */
+  int32_t n_open;
+  double flops_per_slice; /* sum of the steps' flops */
+  double bytes_per_slice; /* sum of the steps' algorithmic bytes */
+  double perm_bytes_per_slice;
+  uint64_t n_slices;      /* 2^n_sliced */
+} stem_plan_summary;
+
+typedef struct stem_plan_s* stem_plan_t;
+
+/* Check a descriptor and compute the step shapes on the host; no device
+ * memory is touched, so this runs without a GPU.  `summary` may be NULL. */
+stem_status stem_plan_validate(const stem_plan_desc* desc, stem_plan_summary* summary);
+
+/* Build a plan: validate, choose the stem's label order before every step
+ * (a permute is planned only where the summed labels are not already the
+ * fastest-varying ones), copy the initial stem and the branches to device
+ * memory owned by the plan (sliced and projected labels moved to the most
+ * significant positions, so each slice's operands are contiguous blocks),
+ * and lay the branches out for the matrix-core kernels.  Host data may be
+ * freed when this returns.  Uses `stream` for the device copies and
+ * synchronises it before returning. */
+stem_status stem_plan_create(const stem_plan_desc* desc, void* stream, stem_plan_t* plan);
+
+/* Release the plan's device memory.  NULL is accepted. */
+stem_status stem_plan_destroy(stem_plan_t plan);
+
+stem_status stem_plan_summary_get(stem_plan_t plan, stem_plan_summary* summary);
+
+/* Bytes of device workspace stem_contract needs: two stem buffers of the
+ * peak size.  The caller allocates it (any 256-byte-aligned device memory). */
+stem_status stem_plan_workspace_bytes(stem_plan_t plan, uint64_t* bytes);
+
+stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* info);
+
+/*
+ * Contract slices [s0, s1) for n_batch projected assignments and sum them
+ * (paper §A.1, slicing: the network value is the sum of the sub-network
+ * values over the assignments of E_s).
+ *   proj_assign: host, n_batch values in [0, 2^n_proj); NULL means one
+ *                assignment 0 for every batch entry.
+ *   out:         device complex128 [n_batch][2^n_open], entry order = the
+ *                plan's open_labels (first most significant).  Overwritten
+ *                with the sum, or added to with STEM_ACCUMULATE.  Each slice
+ *                is added in FP64 in increasing slice order (deterministic).
+ * Asynchronous on `stream`; the plan must not be used on two streams at
+ * once.  An empty range writes zeros (or adds nothing).  s1 > 2^n_sliced
+ * or s0 > s1: STEM_ERANGE.  ws_bytes below stem_plan_workspace_bytes:
+ * STEM_ENOMEM.
+ */
+stem_status stem_contract(stem_plan_t plan, uint64_t s0, uint64_t s1,
+                          const uint64_t* proj_assign, uint32_t n_batch,
+                          void* ws, uint64_t ws_bytes, double* out,
+                          uint32_t flags, void* stream);
+
+/*
+ * Fill dst (device, n complex64) with the counter-based test tensor: entry i
+ * takes SplitMix64 outputs 4i..4i+3 of stream `seed` (Steele, Lea and Flood,
+ * OOPSLA 2014); each 64-bit output gives two 22-bit integers (bits 42-63 and
+ * 10-31); re = (sum of the four integers of outputs 4i, 4i+1) - 2^23, im
+ * likewise from 4i+2, 4i+3; both times 2^-scale_log2 (exact in FP32).
+ */
+stem_status stem_fill_counter(float* dst, uint64_t n, uint64_t seed, int32_t scale_log2,
+                              void* stream);
+
+/*
+ * Linear cross-entropy fidelity (paper §2): out[0] = 2^n_qubits * mean |a|^2 - 1
+ * over the n amplitudes, and out[1] = sum |a|^2; both in FP64.  amps: device
+ * complex128 [n]; out: device double[2].  Deterministic reduction order.
+ */
+stem_status stem_xeb_f64(const double* amps, uint64_t n, int32_t n_qubits, double* out,
+                         void* stream);
+
+const char* stem_status_str(stem_status status);
+const char* stem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STEMGPU_H */

@@ -1,0 +1,367 @@
+// C-ABI of libstemgpu: plan creation, the slice loop of the sliced stem
+// contraction, and utilities.  Paper §A.1 (slicing), §A.2 (stem and
+// branches), §A.3 (branches computed once and shared by every slice).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "stem_internal.h"
+
+namespace stem {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+}  // namespace stem
+
+using namespace stem;
+
+struct StepDev {
+  size_t boff = 0;          // offset of variant 0 in the plan's branch buffer (bytes)
+  size_t bstride = 0;       // bytes per variant
+  int eb_base = 0;          // index of variant 0's scale exponent (split paths)
+};
+
+struct stem_plan_s {
+  PlanLayout L;
+  int precision = STEM_FP32;
+  int device = 0;
+  float* d_stem = nullptr;          // initial stem, fixed labels most significant
+  uint64_t stem_var_elems = 0;      // complex entries per stem variant
+  unsigned char* d_branch = nullptr;
+  std::vector<StepDev> sd;
+  std::vector<int> ebs;             // per step and variant: branch scale exponent
+  std::vector<hipEvent_t> ev;       // 4 per step when timing: perm start/end, gemm start/end
+  std::vector<float> gemm_us, perm_us;
+  bool timed_pending = false;
+};
+
+#define HIPCHK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));               \
+      return STEM_EHIP;                                                           \
+    }                                                                             \
+  } while (0)
+
+static stem_status fail(stem_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+static void free_plan(stem_plan_s* p) {
+  if (!p) return;
+  if (p->d_stem) (void)hipFree(p->d_stem);
+  if (p->d_branch) (void)hipFree(p->d_branch);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  delete p;
+}
+
+extern "C" {
+
+const char* stem_status_str(stem_status s) {
+  switch (s) {
+    case STEM_OK: return "ok";
+    case STEM_EINVAL: return "invalid argument";
+    case STEM_ELABEL: return "label error";
+    case STEM_ESHAPE: return "shape error";
+    case STEM_EUNSUPPORTED: return "unsupported network";
+    case STEM_ENOMEM: return "out of memory or workspace too small";
+    case STEM_ERANGE: return "range error";
+    case STEM_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* stem_last_error(void) { return g_error.c_str(); }
+
+stem_status stem_plan_validate(const stem_plan_desc* desc, stem_plan_summary* summary) {
+  try {
+    PlanLayout L;
+    std::string err;
+    stem_status s = build_layout(desc, &L, &err);
+    if (s != STEM_OK) return fail(s, err);
+    if (summary) *summary = L.summary;
+    return STEM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(STEM_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(STEM_EINVAL, "unexpected host exception");
+  }
+}
+
+static stem_status plan_create_impl(const stem_plan_desc* d, hipStream_t st, stem_plan_s* p) {
+  std::string err;
+  stem_status s = build_layout(d, &p->L, &err);
+  if (s != STEM_OK) return fail(s, err);
+  PlanLayout& L = p->L;
+  p->precision = d->precision;
+  HIPCHK(hipGetDevice(&p->device));
+
+  // ---- initial stem: fixed labels moved to the most significant bits ----
+  const int r0 = d->stem_rank;
+  const uint64_t n0 = 1ull << r0;
+  HIPCHK(hipMalloc(&p->d_stem, n0 * 8));
+  p->stem_var_elems = 1ull << L.stem_rest.size();
+  std::vector<int32_t> stem_order = L.stem_fixed;
+  stem_order.insert(stem_order.end(), L.stem_rest.begin(), L.stem_rest.end());
+  const bool stem_perm = !same_order(L.stem_labels_in, stem_order);
+  if (!stem_perm) {
+    HIPCHK(hipMemcpyAsync(p->d_stem, d->stem_data, n0 * 8,
+                          d->stem_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          st));
+  } else {
+    const float* src = d->stem_data;
+    float* tmp = nullptr;
+    if (!d->stem_on_device) {
+      HIPCHK(hipMalloc(&tmp, n0 * 8));
+      HIPCHK(hipMemcpyAsync(tmp, d->stem_data, n0 * 8, hipMemcpyHostToDevice, st));
+      src = tmp;
+    }
+    const PermArgs pa = make_perm(L.stem_labels_in, stem_order);
+    hipError_t e = launch_permute(src, p->d_stem, pa, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(STEM_EHIP, std::string("stem relayout: ") + hipGetErrorString(e));
+  }
+
+  // ---- branches: host relayout to (fixed, sigma, free), then MFMA layout ----
+  size_t total = 0;
+  p->sd.resize(L.steps.size());
+  std::vector<size_t> data_off(d->n_branches + 1, 0);
+  for (int i = 0; i < d->n_branches; ++i)
+    data_off[i + 1] = data_off[i] + (size_t(1) << d->branch_ranks[i]) * 2;
+  std::vector<size_t> label_off(d->n_branches + 1, 0);
+  for (int i = 0; i < d->n_branches; ++i) label_off[i + 1] = label_off[i] + d->branch_ranks[i];
+  for (size_t i = 0; i < L.steps.size(); ++i) {
+    const StepLayout& S = L.steps[i];
+    const uint64_t nvar = 1ull << S.fixed.size();
+    size_t per = 0;
+    if (p->precision == STEM_FP32)
+      per = bfrag_f32_floats(S.K, S.N) * 4;
+    else
+      per = bfrag_split_halves(S.K, S.N) * 2 * 2;
+    per = (per + 255) & ~size_t(255);
+    p->sd[i].boff = total;
+    p->sd[i].bstride = per;
+    p->sd[i].eb_base = (int)p->ebs.size();
+    p->ebs.resize(p->ebs.size() + nvar, 0);
+    total += per * nvar;
+  }
+  std::vector<unsigned char> hb(std::max<size_t>(total, 256), 0);
+  for (size_t i = 0; i < L.steps.size(); ++i) {
+    const StepLayout& S = L.steps[i];
+    const int bi = S.branch_index;
+    const int r = d->branch_ranks[bi];
+    std::vector<int32_t> from(d->branch_labels + label_off[bi], d->branch_labels + label_off[bi + 1]);
+    std::vector<int32_t> to = S.fixed;
+    to.insert(to.end(), S.sigma.begin(), S.sigma.end());
+    to.insert(to.end(), S.free_labels.begin(), S.free_labels.end());
+    std::vector<float> re((size_t(1) << r) * 2);
+    host_relayout(d->branch_data + data_off[bi], re.data(), from, to);
+    const uint64_t nvar = 1ull << S.fixed.size();
+    const size_t sub = (size_t)(S.K * S.N) * 2;  // floats per variant
+    for (uint64_t v = 0; v < nvar; ++v) {
+      unsigned char* dst = hb.data() + p->sd[i].boff + v * p->sd[i].bstride;
+      if (p->precision == STEM_FP32) {
+        build_bfrag_f32(re.data() + v * sub, S.K, S.N, (float*)dst);
+      } else {
+        p->ebs[p->sd[i].eb_base + v] = build_bfrag_split(re.data() + v * sub, S.K, S.N,
+                                                         p->precision == STEM_SPLIT_BF16,
+                                                         (uint16_t*)dst);
+      }
+    }
+  }
+  HIPCHK(hipMalloc(&p->d_branch, hb.size()));
+  HIPCHK(hipMemcpyAsync(p->d_branch, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  p->gemm_us.assign(L.steps.size(), -1.f);
+  p->perm_us.assign(L.steps.size(), -1.f);
+  return STEM_OK;
+}
+
+stem_status stem_plan_create(const stem_plan_desc* desc, void* stream, stem_plan_t* plan) {
+  if (!plan) return fail(STEM_EINVAL, "null plan output");
+  *plan = nullptr;
+  stem_plan_s* p = nullptr;
+  try {
+    p = new stem_plan_s();
+    stem_status s = plan_create_impl(desc, (hipStream_t)stream, p);
+    if (s != STEM_OK) {
+      free_plan(p);
+      return s;
+    }
+  } catch (const std::bad_alloc&) {
+    free_plan(p);
+    return fail(STEM_ENOMEM, "host allocation failed");
+  } catch (...) {
+    free_plan(p);
+    return fail(STEM_EINVAL, "unexpected host exception");
+  }
+  *plan = p;
+  return STEM_OK;
+}
+
+stem_status stem_plan_destroy(stem_plan_t plan) {
+  free_plan(plan);
+  return STEM_OK;
+}
+
+stem_status stem_plan_summary_get(stem_plan_t plan, stem_plan_summary* summary) {
+  if (!plan || !summary) return fail(STEM_EINVAL, "null argument");
+  *summary = plan->L.summary;
+  return STEM_OK;
+}
+
+stem_status stem_plan_workspace_bytes(stem_plan_t plan, uint64_t* bytes) {
+  if (!plan || !bytes) return fail(STEM_EINVAL, "null argument");
+  const uint64_t one = plan->L.steps.empty() ? 0 : ((8ull << plan->L.max_ws_rank) + 255) & ~255ull;
+  *bytes = std::max<uint64_t>(2 * one, 256);
+  return STEM_OK;
+}
+
+stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* info) {
+  if (!plan || !info) return fail(STEM_EINVAL, "null argument");
+  if (step < 0 || step >= (int32_t)plan->L.steps.size())
+    return fail(STEM_ERANGE, "step index out of range");
+  const StepLayout& S = plan->L.steps[step];
+  std::memset(info, 0, sizeof(*info));
+  info->rank_in = S.rank_in;
+  info->rank_out = S.rank_out;
+  info->n_shared = S.s;
+  info->n_free = S.f;
+  info->permuted = S.permuted ? 1 : 0;
+  info->M = S.M;
+  info->K = S.K;
+  info->N = S.N;
+  const double M = (double)S.M, K = (double)S.K, N = (double)S.N;
+  info->flops = 8.0 * M * K * N;
+  info->bytes = 8.0 * (M * K + M * N + K * N);
+  info->perm_bytes = S.permuted ? 16.0 * (double)(1ull << S.rank_in) : 0.0;
+  if (plan->timed_pending) {
+    // resolve the events of the last timed call (the caller synchronised)
+    for (size_t i = 0; i < plan->L.steps.size(); ++i) {
+      float ms = -1.f;
+      if (hipEventElapsedTime(&ms, plan->ev[4 * i + 2], plan->ev[4 * i + 3]) == hipSuccess)
+        plan->gemm_us[i] = ms * 1000.f;
+      if (plan->L.steps[i].permuted &&
+          hipEventElapsedTime(&ms, plan->ev[4 * i], plan->ev[4 * i + 1]) == hipSuccess)
+        plan->perm_us[i] = ms * 1000.f;
+    }
+    plan->timed_pending = false;
+  }
+  info->last_gemm_us = plan->gemm_us[step];
+  info->last_perm_us = plan->perm_us[step];
+  return STEM_OK;
+}
+
+static stem_status run_gemm(stem_plan_s* p, size_t i, uint64_t var, const float* in, float* out,
+                            hipStream_t st) {
+  const StepLayout& S = p->L.steps[i];
+  const unsigned char* b = p->d_branch + p->sd[i].boff + var * p->sd[i].bstride;
+  hipError_t e;
+  if (p->precision == STEM_FP32)
+    e = launch_cgemm_f32(in, (const float*)b, out, S.M, S.K, S.N, S.gemm, st);
+  else
+    e = launch_cgemm_split(in, (const uint16_t*)b, p->ebs[p->sd[i].eb_base + var], out, S.M,
+                           S.K, S.N, p->precision == STEM_SPLIT_BF16, S.gemm, st);
+  if (e != hipSuccess) return fail(STEM_EHIP, std::string("product kernel: ") + hipGetErrorString(e));
+  return STEM_OK;
+}
+
+stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_t* proj_assign,
+                          uint32_t n_batch, void* ws, uint64_t ws_bytes, double* out,
+                          uint32_t flags, void* stream) {
+  if (!p || !out) return fail(STEM_EINVAL, "null plan or output");
+  hipStream_t st = (hipStream_t)stream;
+  const PlanLayout& L = p->L;
+  const int n_sl = (int)L.sliced.size(), n_pr = (int)L.proj.size();
+  const uint64_t n_slices = 1ull << n_sl;
+  if (s0 > s1 || s1 > n_slices) return fail(STEM_ERANGE, "slice range outside [0, 2^n_sliced)");
+  if (n_batch == 0) return STEM_OK;
+  if (proj_assign)
+    for (uint32_t b = 0; b < n_batch; ++b)
+      if (n_pr < 64 && proj_assign[b] >= (1ull << n_pr))
+        return fail(STEM_ERANGE, "projected assignment out of range");
+  uint64_t need = 0;
+  stem_plan_workspace_bytes(p, &need);
+  if (!L.steps.empty() && (!ws || ws_bytes < need))
+    return fail(STEM_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                 std::to_string(need));
+  const uint64_t n_out = 1ull << L.open.size();
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != p->device) return fail(STEM_EINVAL, "plan was created on another device");
+  if (!(flags & STEM_ACCUMULATE)) {
+    hipError_t e = launch_zero_f64(out, 2 * n_out * n_batch, st);
+    if (e != hipSuccess) return fail(STEM_EHIP, std::string("zero: ") + hipGetErrorString(e));
+  }
+  if (s0 == s1) return STEM_OK;
+  const bool timing = (flags & STEM_TIME_STEPS) != 0;
+  if (timing && p->ev.empty()) {
+    p->ev.resize(4 * L.steps.size());
+    for (auto& e : p->ev) HIPCHK(hipEventCreate(&e));
+  }
+  const uint64_t half = need / 2;
+  float* buf[2] = {(float*)ws, (float*)((unsigned char*)ws + half)};
+  for (uint32_t b = 0; b < n_batch; ++b) {
+    const uint64_t pa = proj_assign ? proj_assign[b] : 0;
+    for (uint64_t s = s0; s < s1; ++s) {
+      const bool time_this = timing && b + 1 == n_batch && s + 1 == s1;
+      const uint64_t sv = variant_index(L.stem_fixed_src, s, pa, n_sl, n_pr);
+      const float* cur = p->d_stem + 2 * sv * p->stem_var_elems;
+      int cur_buf = -1;
+      for (size_t i = 0; i < L.steps.size(); ++i) {
+        const StepLayout& S = L.steps[i];
+        if (S.permuted) {
+          const int dst = cur_buf == 0 ? 1 : 0;
+          if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i], st));
+          hipError_t e = launch_permute(cur, buf[dst], S.perm, st);
+          if (e != hipSuccess) return fail(STEM_EHIP, std::string("permute: ") + hipGetErrorString(e));
+          if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 1], st));
+          cur = buf[dst];
+          cur_buf = dst;
+        }
+        const int dst = cur_buf == 0 ? 1 : 0;
+        const uint64_t var = variant_index(S.fixed_src, s, pa, n_sl, n_pr);
+        if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 2], st));
+        stem_status rs = run_gemm(p, i, var, cur, buf[dst], st);
+        if (rs != STEM_OK) return rs;
+        if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 3], st));
+        cur = buf[dst];
+        cur_buf = dst;
+      }
+      hipError_t e = launch_acc_f64(cur, out + 2 * n_out * b, L.final_map, st);
+      if (e != hipSuccess) return fail(STEM_EHIP, std::string("accumulate: ") + hipGetErrorString(e));
+    }
+  }
+  if (timing) p->timed_pending = true;
+  return STEM_OK;
+}
+
+stem_status stem_fill_counter(float* dst, uint64_t n, uint64_t seed, int32_t scale_log2,
+                              void* stream) {
+  if (!dst && n) return fail(STEM_EINVAL, "null destination");
+  hipError_t e = launch_fill_counter(dst, n, seed, scale_log2, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(STEM_EHIP, std::string("fill: ") + hipGetErrorString(e));
+  return STEM_OK;
+}
+
+stem_status stem_xeb_f64(const double* amps, uint64_t n, int32_t n_qubits, double* out,
+                         void* stream) {
+  if ((!amps && n) || !out) return fail(STEM_EINVAL, "null argument");
+  if (n_qubits < 0 || n_qubits > 1000) return fail(STEM_EINVAL, "bad qubit count");
+  hipError_t e = launch_xeb_f64(amps, n, n_qubits, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(STEM_EHIP, std::string("xeb: ") + hipGetErrorString(e));
+  return STEM_OK;
+}
+
+}  // extern "C"

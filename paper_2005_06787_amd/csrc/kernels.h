@@ -1,0 +1,51 @@
+// Launchers of the libstemgpu kernels (gfx950) and the host-side layout of
+// branch operands they read.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stem_internal.h"
+
+namespace stem {
+
+// ---- branch operand layouts (host) -------------------------------------
+//
+// A complex product C[M x N] = A[M x K] . B[K x N] is run as the real
+// product [M x 2K] . [2K x 2N] on interleaved (re, im) data, with every
+// complex branch entry b = br + i bi expanded to the 2x2 block
+//     [[ br, bi],
+//      [-bi, br]]   (rows: re/im part of A; columns: re/im part of C),
+// so that C's interleaved (re, im) columns come out directly.
+
+// FP32 path: fragment order for the 16x16x4 f32 MFMA.  Kp = max(16, 2K),
+// Np = max(16, 2N); element ((kc*NT + nt)*4 + j)*64 + lane holds the
+// expanded B'[16 kc + 4 (lane/16) + j][16 nt + lane%16] (zero padded).
+size_t bfrag_f32_floats(int64_t K, int64_t N);
+void build_bfrag_f32(const float* b, int64_t K, int64_t N, float* out);
+
+// Split paths: fragment order for the 16x16x32 f16/bf16 MFMA.  Kq =
+// max(32, 2K), Np = max(16, 2N); 8 consecutive halves per lane:
+// element (((kc*NT + nt)*64 + lane)*8 + i) holds B'[32 kc + 8 (lane/16) + i]
+// [16 nt + lane%16].  hi and lo parts are stored one after the other; the
+// FP16 variant scales B by 2^eb first (eb chosen so that max |B'| 2^eb lies
+// in [2^13, 2^14)), the BF16 variant uses eb = 0.
+size_t bfrag_split_halves(int64_t K, int64_t N);  // per part (hi or lo)
+// Writes hi then lo (2 * bfrag_split_halves uint16 values); returns eb.
+int build_bfrag_split(const float* b, int64_t K, int64_t N, int bf16, uint16_t* out);
+
+// ---- launchers ---------------------------------------------------------
+hipError_t launch_permute(const float* in, float* out, const PermArgs& p, hipStream_t st);
+hipError_t launch_cgemm_f32(const float* A, const float* Bf, float* C, int64_t M, int64_t K,
+                            int64_t N, const GemmLayout& lay, hipStream_t st);
+hipError_t launch_cgemm_split(const float* A, const uint16_t* Bhl, int eb, float* C,
+                              int64_t M, int64_t K, int64_t N, int bf16, const GemmLayout& lay,
+                              hipStream_t st);
+hipError_t launch_acc_f64(const float* in, double* out, const BitMap& m, hipStream_t st);
+hipError_t launch_zero_f64(double* p, uint64_t n, hipStream_t st);
+hipError_t launch_fill_counter(float* dst, uint64_t n, uint64_t seed, int scale_log2,
+                               hipStream_t st);
+hipError_t launch_xeb_f64(const double* amps, uint64_t n, int n_qubits, double* out,
+                          hipStream_t st);
+
+}  // namespace stem

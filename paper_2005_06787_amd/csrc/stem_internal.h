@@ -1,0 +1,132 @@
+// Internal declarations shared by the host planner, the kernels and the
+// C-ABI layer of libstemgpu.  Nothing here is part of the public interface.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/stemgpu.h"
+
+namespace stem {
+
+constexpr int kDefaultMaxRank = 33;
+constexpr int kPermTileLowBits = 5;   // output and input runs of 32 entries (256 B)
+constexpr int kPermTileMaxBits = 10;  // at most 1024 entries per permute tile
+
+// Bit permutation of a rank-r tensor, in the form the permute kernel takes.
+// Input address bit p (0 = least significant) moves to output bit dst[p].
+// Tile bits (tin, ascending) are staged through LDS; the others index the
+// workgroup.
+struct PermArgs {
+  int32_t rank;
+  int32_t t;            // tile bits
+  int32_t nn;           // non-tile bits = rank - t
+  int32_t pad;
+  int32_t tin[16];      // input positions of the tile bits, ascending
+  int32_t tout[16];     // output positions of the tile bits, ascending
+  int32_t f2e[16];      // output-order tile bit i is input-order tile bit f2e[i]
+  int32_t nin[64];      // input positions of the non-tile bits, ascending
+  int32_t nout[64];     // their output positions
+};
+
+// Destination bit of every source bit, for the final reorder into the
+// open-label order (rank <= 63).
+struct BitMap {
+  int32_t rank;
+  int32_t dst[63];
+};
+
+// Operand addressing of one product (see the kernels): amode 0 = K-fast
+// (summed labels are the s fastest stem bits), 1 = M-fast (the 4 fastest
+// stem bits are not summed; summed labels anywhere); cmode 0 = N-fast (new
+// labels fastest in the output), 1 = M-fast (output keeps the 4 fastest row
+// labels fastest, new labels just above them).
+struct GemmLayout {
+  int32_t amode, cmode, s, f;
+  int32_t spos[16];     // stem address position of k bit i (i = 0 least significant)
+  int32_t sins[16];     // the same positions, ascending
+};
+
+struct GemmGeom {
+  int64_t M;
+  int32_t K, N, Kr, Nr, KC, NT, s, f;
+  int32_t spos[16];
+  int32_t sins[16];
+};
+
+constexpr int kMaxShared = 16;  // K <= 2^16
+constexpr int kMaxFree = 16;    // N <= 2^16
+
+// Where the value of a fixed (sliced or projected) label comes from.
+struct FixedSrc {
+  int32_t is_proj;      // 0: sliced label, 1: projected label
+  int32_t index;        // position in sliced_labels / proj_labels
+};
+
+struct StepLayout {
+  int32_t rank_in = 0, rank_out = 0, s = 0, f = 0;
+  bool permuted = false;
+  std::vector<int32_t> labels_before;  // stem order entering the step
+  std::vector<int32_t> labels_gemm;    // stem order read by the product
+  std::vector<int32_t> labels_after;   // stem order written by the product
+  std::vector<int32_t> sigma;          // summed labels, K index order (first = MSB)
+  std::vector<int32_t> free_labels;    // new labels, N index order (first = MSB)
+  std::vector<int32_t> fixed;          // branch labels fixed per slice/batch, MSB first
+  std::vector<FixedSrc> fixed_src;
+  int32_t branch_index = 0;
+  int64_t M = 0, K = 0, N = 0;
+  GemmLayout gemm{};
+  PermArgs perm{};                     // valid when permuted
+};
+
+struct PlanLayout {
+  std::vector<int32_t> open, sliced, proj;
+  std::vector<int32_t> stem_labels_in;   // as given
+  std::vector<int32_t> stem_fixed;       // stem's fixed labels, MSB first
+  std::vector<FixedSrc> stem_fixed_src;
+  std::vector<int32_t> stem_rest;        // stem's other labels, original order
+  std::vector<StepLayout> steps;
+  std::vector<int32_t> final_labels;
+  BitMap final_map{};
+  int32_t peak_rank = 0;       // over every stem the steps read or write
+  int32_t max_ws_rank = 0;     // largest tensor written to the workspace
+  int32_t max_rank = kDefaultMaxRank;
+  stem_plan_summary summary{};
+};
+
+// Build the layout of a descriptor on the host.  Returns a status and sets
+// *err on failure.
+stem_status build_layout(const stem_plan_desc* d, PlanLayout* out, std::string* err);
+
+// Bit permutation that re-stores a tensor from C order over `from` to C
+// order over `to` (both permutations of one label set).
+PermArgs make_perm(const std::vector<int32_t>& from, const std::vector<int32_t>& to);
+
+// True when `from` and `to` are the same order.
+bool same_order(const std::vector<int32_t>& from, const std::vector<int32_t>& to);
+
+// Host reorder of a complex64 tensor (2 floats per entry) from C order over
+// `from` to C order over `to`.
+void host_relayout(const float* src, float* dst, const std::vector<int32_t>& from,
+                   const std::vector<int32_t>& to);
+
+// Value (0/1) of a fixed label for slice id s and projected assignment p.
+inline int fixed_bit(const FixedSrc& fs, uint64_t s, uint64_t p, int n_sliced, int n_proj) {
+  if (fs.is_proj) return (int)((p >> (n_proj - 1 - fs.index)) & 1ull);
+  return (int)((s >> (n_sliced - 1 - fs.index)) & 1ull);
+}
+
+inline uint64_t variant_index(const std::vector<FixedSrc>& src, uint64_t s, uint64_t p,
+                              int n_sliced, int n_proj) {
+  uint64_t v = 0;
+  for (const FixedSrc& fs : src) v = (v << 1) | (uint64_t)fixed_bit(fs, s, p, n_sliced, n_proj);
+  return v;
+}
+
+// Thread-local error message of the C-ABI.
+void set_error(const std::string& msg);
+
+}  // namespace stem

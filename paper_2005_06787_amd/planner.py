@@ -1,0 +1,248 @@
+"""Stem planner: circuit -> sliced stem network (host side, not timed).
+
+Plan creation is preprocessing; the paper excludes it from its runtimes
+(§A.4) and pre-computes the branches on the host (§A.3).  The paper finds
+the stem with hypergraph partitioning and local search (§4, §A.2); this
+planner is a simpler stand-in that produces the same kind of object, a
+slicing scheme (E_s, T) whose tree T is a stem (§A.1, §A.2):
+
+1. Build the circuit's network and absorb rank <= 2 tensors (circuit_tn).
+2. Linear stem order: start from a random tensor and repeatedly absorb the
+   neighbouring tensor that leaves the smallest stem (ties: the one sharing
+   the most labels; then random), over many seeded trials.  A trial is
+   scored after step 3 by (peak width, time complexity tc).
+3. Greedy slicing (§4, §A.2 dynamic slicing): add the label, among those on
+   the widest stems, whose removal gives the smallest tc (ties: lowest
+   label), until the width target or the sliced-label count is met.
+   tc((E_s, T)) = 2^|E_s| * sum over steps of 2^|E_step \\ E_s| (§A.1).
+4. The first tensors of the order are pre-contracted into the initial stem
+   while its rank stays small; the rest are grouped into branches, merging
+   consecutive tensors while a roofline time model of the step says one
+   larger product is faster than two (§A.3, branch merging), up to a
+   branch rank limit.
+5. Branches and the initial stem are contracted on the host in FP64 and
+   stored as complex64 (§A.3: computed once, shared by all slices).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .circuit_tn import circuit_network, contract_two, simplify
+
+# Roofline model of one step on one MI355X (used to decide branch merges).
+HBM_BYTES_PER_S = 5.0e12      # sustained stream rate, below the 8 TB/s peak
+MFMA_FP32_FLOPS = 1.0e14      # sustained FP32 MFMA rate, below the 157 TF peak
+LAUNCH_S = 4.0e-6             # per kernel launch
+
+
+def step_time(r_in: int, s: int, f: int, permuted: bool = False) -> float:
+    """Modelled seconds of one stem step: stem rank r_in, s summed, f new."""
+    m = 2.0 ** (r_in - s)
+    k, n = 2.0 ** s, 2.0 ** f
+    t_mem = 8.0 * (m * k + m * n + k * n) / HBM_BYTES_PER_S
+    t_flop = 8.0 * m * k * n / MFMA_FP32_FLOPS
+    t = max(t_mem, t_flop) + LAUNCH_S
+    if permuted:
+        t += 16.0 * m * k / HBM_BYTES_PER_S + LAUNCH_S
+    return t
+
+
+class _Order:
+    """A linear order with per-step label sets, for fast slicing updates."""
+
+    def __init__(self, tlabels, order):
+        self.order = list(order)
+        stems, unions = [], []
+        stem = set(tlabels[order[0]])
+        stems.append(frozenset(stem))
+        for j in order[1:]:
+            t = tlabels[j]
+            unions.append(frozenset(stem | t))
+            stem = stem ^ t
+            stems.append(frozenset(stem))
+        self.stems = stems        # stem after absorbing order[0..k]
+        self.unions = unions      # labels of step k (stem before + tensor)
+
+    def widths(self, sliced=frozenset()):
+        return [len(s - sliced) for s in self.stems]
+
+    def tc(self, sliced=frozenset()):
+        return (2.0 ** len(sliced)) * sum(2.0 ** len(u - sliced) for u in self.unions)
+
+
+def _linear_order(tlabels, owners, rng, noise=0.5):
+    n = len(tlabels)
+    start = int(rng.integers(n))
+    stem = set(tlabels[start])
+    order = [start]
+    remaining = set(range(n))
+    remaining.discard(start)
+    while remaining:
+        cands = set()
+        for x in stem:
+            for j in owners.get(x, ()):
+                if j in remaining:
+                    cands.add(j)
+        if not cands:
+            cands = remaining
+        best, best_key = None, None
+        for j in cands:
+            t = tlabels[j]
+            key = (len(stem ^ t) + noise * rng.random(), -len(stem & t))
+            if best_key is None or key < best_key:
+                best, best_key = j, key
+        stem ^= tlabels[best]
+        order.append(best)
+        remaining.discard(best)
+    return order
+
+
+def greedy_slice(od: _Order, n_sliced=None, max_width=None, forbid=()):
+    """Greedy slicing of a linear order (ties: lowest label)."""
+    sliced = set()
+    forbid = set(forbid)
+    while True:
+        w = od.widths(frozenset(sliced))
+        peak = max(w)
+        if n_sliced is not None and len(sliced) >= n_sliced:
+            break
+        if n_sliced is None and (max_width is None or peak <= max_width):
+            break
+        cands = set()
+        for s, wk in zip(od.stems, w):
+            if wk == peak:
+                cands |= set(s)
+        cands -= sliced
+        cands -= forbid
+        if not cands:
+            break
+        best, best_key = None, None
+        for x in sorted(cands):
+            trial = frozenset(sliced | {x})
+            key = (max(od.widths(trial)), od.tc(trial))
+            if best_key is None or key < best_key:
+                best, best_key = x, key
+        sliced.add(best)
+    return sorted(sliced)
+
+
+def find_scheme(tlabels, trials: int, seed: int, n_sliced=None, max_width=None, forbid=()):
+    """Best linear order + slicing over seeded trials: (order, sliced, peak, tc)."""
+    owners: dict = {}
+    for i, lab in enumerate(tlabels):
+        for x in lab:
+            owners.setdefault(x, []).append(i)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    best = None
+    for _ in range(trials):
+        order = _linear_order(tlabels, owners, rng)
+        od = _Order(tlabels, order)
+        sl = greedy_slice(od, n_sliced=n_sliced, max_width=max_width, forbid=forbid)
+        fs = frozenset(sl)
+        key = (max(od.widths(fs)), od.tc(fs))
+        if best is None or key < best[0]:
+            best = (key, order, sl)
+    (peak, tc), order, sl = best
+    return order, sl, peak, tc
+
+
+def _group_labels(tlabels, group):
+    acc = set()
+    for j in group:
+        acc ^= tlabels[j]
+    return acc
+
+
+def group_branches(tlabels, order, n_init: int, fixed: set, max_branch_rank: int = 12,
+                   merge: bool = True):
+    """Split order[n_init:] into consecutive groups (merged branches)."""
+    stem = _group_labels(tlabels, order[:n_init]) - fixed
+    groups = []
+    cur = []
+    cur_lab = set()
+
+    def cost(st, lab):
+        s = len(st & lab)
+        f = len(lab - st)
+        return step_time(len(st), s, f)
+
+    for j in order[n_init:]:
+        t = tlabels[j] - fixed
+        if not cur:
+            cur, cur_lab = [j], set(t)
+            continue
+        merged = cur_lab ^ t
+        ok = merge and len(merged) <= max_branch_rank
+        if ok:
+            after_cur = stem ^ cur_lab
+            t_sep = cost(stem, cur_lab) + cost(after_cur, t)
+            t_merged = cost(stem, merged)
+            ok = t_merged <= t_sep
+        if ok:
+            cur.append(j)
+            cur_lab = merged
+        else:
+            groups.append(cur)
+            stem = stem ^ cur_lab
+            cur, cur_lab = [j], set(t)
+    if cur:
+        groups.append(cur)
+    return groups
+
+
+def _contract_group(tensors, group, keep):
+    acc = tensors[group[0]]
+    for j in group[1:]:
+        acc = contract_two(acc, tensors[j], keep)
+    return acc
+
+
+def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=(), *,
+                 n_sliced=None, max_width=None, trials: int = 64, seed: int = 0,
+                 init_rank: int = 12, max_branch_rank: int = 12, merge: bool = True) -> dict:
+    """Sliced stem network of a circuit's amplitudes.
+
+    ``open_qubits`` stay open (result index, first qubit most significant),
+    ``proj_qubits`` are fixed per batch entry (projected assignment bits in
+    the same order), the other qubits are closed with ``closed_bits``.
+    Returns the network dictionary plus a "stats" entry.
+    """
+    net = simplify(circuit_network(circuit, open_qubits, closed_bits, proj_qubits))
+    ids = sorted(net.tensors)
+    tensors = [net.tensors[i] for i in ids]
+    proj = set(net.proj_labels)
+    tlabels = [frozenset(x for x in lab if x not in proj) for lab, _ in tensors]
+    forbid = set(net.open_labels)
+    order, sliced, peak, tc = find_scheme(tlabels, trials, seed, n_sliced=n_sliced,
+                                          max_width=max_width, forbid=forbid)
+    fixed = set(sliced) | proj
+    # initial stem: absorb while the (unfixed) rank stays within init_rank
+    n_init = 1
+    stem_lab = set(tlabels[order[0]]) - fixed
+    while n_init < len(order):
+        nxt = stem_lab ^ (tlabels[order[n_init]] - fixed)
+        if len(nxt) > init_rank:
+            break
+        stem_lab = nxt
+        n_init += 1
+    groups = group_branches(tlabels, order, n_init, fixed, max_branch_rank, merge)
+    keep = set(sliced)
+    stem = _contract_group(tensors, order[:n_init], keep)
+    branches = []
+    for g in groups:
+        lab, data = _contract_group(tensors, g, keep)
+        branches.append({"labels": [int(x) for x in lab], "data": data.astype(np.complex64)})
+    return {
+        "open_labels": [int(x) for x in net.open_labels],
+        "sliced_labels": [int(x) for x in sliced],
+        "proj_labels": [int(x) for x in net.proj_labels],
+        "stem": {"labels": [int(x) for x in stem[0]], "data": stem[1].astype(np.complex64)},
+        "branches": branches,
+        "stats": {"peak_width": int(peak), "tc": float(tc),
+                  "log2_tc": float(math.log2(tc)) if tc > 0 else 0.0,
+                  "n_tensors": len(tensors), "n_branches": len(branches),
+                  "n_init": n_init},
+    }

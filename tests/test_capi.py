@@ -1,0 +1,102 @@
+"""Host-side checks of libstemgpu: it loads, exports every declared symbol,
+and its host planner computes the step shapes of paper §A.1 (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2005_06787_amd import _capi as C
+from paper_2005_06787_amd import stem_plan_validate
+from workloads.networks import random_stem_network
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "stemgpu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stem_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    handle = ctypes.CDLL(C.LIB_PATH)
+    for name in names:
+        assert hasattr(handle, name), name
+    # and the binding declares a signature for each of them
+    assert set(names) <= set(C.SIGNATURES)
+
+
+def _expected_steps(net):
+    """Step shapes recomputed from the label lists (paper §A.1 step cost)."""
+    fixed = set(net["sliced_labels"]) | set(net["proj_labels"])
+    cur = [x for x in net["stem"]["labels"] if x not in fixed]
+    peak = len(cur)
+    out = []
+    for b in net["branches"]:
+        lab = [x for x in b["labels"] if x not in fixed]
+        shared = [x for x in cur if x in lab]
+        free = [x for x in lab if x not in cur]
+        s, f = len(shared), len(free)
+        out.append((len(cur) - s, s, f))
+        cur = [x for x in cur if x not in shared] + free
+        peak = max(peak, len(cur))
+    return out, peak
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_validate_step_shapes(seed):
+    net = random_stem_network(seed, stem_rank=9, n_steps=7, n_open_final=5)
+    summ = stem_plan_validate(net)
+    steps, peak = _expected_steps(net)
+    assert summ["n_steps"] == len(steps)
+    assert summ["peak_rank"] == peak
+    assert summ["n_slices"] == 1 << len(net["sliced_labels"])
+    flops = sum(8.0 * 2 ** (m + s + f) for m, s, f in steps)
+    nbytes = sum(8.0 * (2 ** (m + s) + 2 ** (m + f) + 2 ** (s + f)) for m, s, f in steps)
+    assert summ["flops_per_slice"] == flops
+    assert summ["bytes_per_slice"] == nbytes
+
+
+def _tiny():
+    rng = np.random.Generator(np.random.PCG64(0))
+    d = lambda r: rng.standard_normal((2,) * r) + 0j  # noqa: E731
+    return {"open_labels": [3], "sliced_labels": [], "proj_labels": [],
+            "stem": {"labels": [0, 1], "data": d(2)},
+            "branches": [{"labels": [1, 2], "data": d(2)},
+                         {"labels": [0, 2, 3], "data": d(3)}]}
+
+
+def test_validate_accepts_tiny():
+    s = stem_plan_validate(_tiny())
+    assert s["n_steps"] == 2 and s["n_open"] == 1
+
+
+def test_error_codes():
+    net = _tiny()
+    bad = dict(net, open_labels=[2])            # 2 joins two tensors, 3 dangles
+    with pytest.raises(C.StemError) as e:
+        stem_plan_validate(bad)
+    assert e.value.status == C.STEM_ELABEL
+    bad = dict(net, branches=net["branches"] + [{"labels": [1], "data": np.ones(2)}])
+    with pytest.raises(C.StemError) as e:       # label 1 in three tensors
+        stem_plan_validate(bad)
+    assert e.value.status == C.STEM_ELABEL
+    with pytest.raises(C.StemError) as e:
+        stem_plan_validate(net, max_rank=1)     # stem of rank 2
+    assert e.value.status == C.STEM_ESHAPE
+    bad = dict(net, sliced_labels=[3])          # open and sliced at once
+    with pytest.raises(C.StemError) as e:
+        stem_plan_validate(bad)
+    assert e.value.status == C.STEM_ELABEL
+    assert C.lib().stem_plan_validate(None, None) == C.STEM_EINVAL
+    assert b"null" in C.lib().stem_last_error()
+
+
+def test_status_strings():
+    for s in range(8):
+        assert C.lib().stem_status_str(s)

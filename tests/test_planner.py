@@ -1,0 +1,82 @@
+"""The host planner's stem networks, checked by the oracle (CPU only).
+
+The planner (product code, paper §A.1-§A.3 preprocessing) writes a sliced
+stem network; the oracle contracts that network in FP64, slice by slice
+(``stemnet``), and the sum over slices must equal the state-vector
+amplitudes of the same circuit (paper §A.1: slicing leaves the value
+unchanged; §3: the network's value is the amplitude batch).
+"""
+import numpy as np
+import pytest
+
+from oracle import gates as ogates
+from oracle import stats, statevector, stemnet
+from paper_2005_06787_amd import circuit_tn, planner
+from workloads import circuits as wc
+from workloads import tensors as wt
+
+
+def _c128(net):
+    out = dict(net)
+    out["stem"] = {"labels": net["stem"]["labels"],
+                   "data": np.asarray(net["stem"]["data"], np.complex128)}
+    out["branches"] = [{"labels": b["labels"], "data": np.asarray(b["data"], np.complex128)}
+                       for b in net["branches"]]
+    return out
+
+
+def test_product_gates_equal_oracle_gates():
+    for name in ("sqrt_x", "sqrt_y", "sqrt_w", "id"):
+        assert np.allclose(circuit_tn.single_qubit_gate(name), ogates.gate_1q(name), atol=1e-15)
+    assert np.allclose(circuit_tn.fsim_gate(np.pi / 2, np.pi / 6), ogates.fsim(np.pi / 2, np.pi / 6),
+                       atol=1e-15)
+    assert np.allclose(circuit_tn.fsim_gate(0.3, 0.7), ogates.fsim(0.3, 0.7), atol=1e-15)
+
+
+@pytest.mark.parametrize("rows,cols,cycles,seed,n_sliced", [
+    (2, 3, 4, 1, 0), (3, 3, 5, 2, 2), (3, 3, 6, 3, 3), (2, 4, 8, 4, 1)])
+def test_plan_sliced_sum_equals_statevector(rows, cols, cycles, seed, n_sliced):
+    c = wc.make_circuit(rows, cols, cycles, seed)
+    n = c["n_qubits"]
+    psi = statevector.run(c)
+    open_q = [0, n - 1]
+    proj_q = [1, n - 2]
+    closed = {q: (q * 7 + seed) % 2 for q in range(n) if q not in open_q + proj_q}
+    net = planner.plan_circuit(c, open_q, closed, proj_q, n_sliced=n_sliced, trials=4, seed=seed,
+                               init_rank=4, max_branch_rank=6)
+    assert len(net["sliced_labels"]) == n_sliced
+    onet = _c128(net)
+    for p in range(4):
+        bits = {proj_q[0]: (p >> 1) & 1, proj_q[1]: p & 1}
+        cb = {**closed, **bits}
+        closed_q = sorted(cb)
+        ref = statevector.batch_amplitudes(psi, n, open_q, closed_q, [cb[q] for q in closed_q])
+        got = stemnet.sliced_sum(onet, proj=p).reshape(-1)
+        assert stats.rel_l2(got, ref) < 1e-6   # complex64 storage of the tensors
+
+
+def test_small_config_plan_matches_statevector():
+    """4x5 grid, 8 cycles: 6 open qubits at rows 0-1, cols 2-4, seeded prefix."""
+    c = wc.make_circuit(4, 5, 8, seed=1)
+    open_q = wc.block_qubits(4, 5, range(0, 2), range(2, 5))
+    pre = wt.split_open_prefix(20, open_q, 1001)
+    closed = dict(zip(pre["closed"], pre["closed_bits"]))
+    for n_sliced in (0, 4):
+        net = planner.plan_circuit(c, open_q, closed, n_sliced=n_sliced, trials=8, seed=0)
+        got = stemnet.sliced_sum(_c128(net)).reshape(-1)
+        psi = statevector.run(c)
+        ref = statevector.batch_amplitudes(psi, 20, open_q, pre["closed"], pre["closed_bits"])
+        assert stats.rel_l2(got, ref) < 1e-6
+
+
+def test_slicing_cost_identity():
+    """tc((E_s, T)) = 2^|E_s| * tc of the network with E_s removed (paper §A.1)."""
+    c = wc.make_circuit(3, 4, 6, seed=5)
+    net = circuit_tn.simplify(circuit_tn.circuit_network(c, [0, 1], {q: 0 for q in range(2, 12)}))
+    tl = [frozenset(lab) for lab, _ in net.tensors.values()]
+    order, sliced, peak, tc = planner.find_scheme(tl, trials=2, seed=0, n_sliced=3)
+    od = planner._Order(tl, order)
+    removed = [frozenset(x - set(sliced)) for x in tl]
+    od2 = planner._Order(removed, order)
+    assert tc == pytest.approx(8 * od2.tc())
+    assert peak == max(od2.widths())
