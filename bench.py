@@ -66,10 +66,17 @@ def timed_run(plan, steps, warmup, n_slices, stream):
 
 
 def roofline(plan):
+    """Dominant kernel (the product) from the hipEvents of the last timed call.
+
+    One product launch covers ``last_slices`` slices of one step; its
+    algorithmic bytes are that many times the step's 8 (MK + MN + KN).
+    """
     steps = plan.steps()
-    g_bytes = sum(s["bytes"] for s in steps)
+    nz = steps[0]["last_slices"]
+    g_bytes = nz * sum(s["bytes"] for s in steps)
+    g_flops = nz * sum(s["flops"] for s in steps)
     g_us = sum(s["last_gemm_us"] for s in steps)
-    p_bytes = sum(s["perm_bytes"] for s in steps)
+    p_bytes = nz * sum(s["perm_bytes"] for s in steps)
     p_us = sum(s["last_perm_us"] for s in steps if s["permuted"])
     launches = len(steps)
     achieved = g_bytes / (g_us * 1e-6) / 1e9
@@ -81,10 +88,12 @@ def roofline(plan):
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None,
+        "slices_per_launch": nz,
         "bytes_per_launch": g_bytes / launches,
         "avg_launch_us": g_us / launches,
-        "permute": {"achieved": round(p_bytes / (p_us * 1e-6) / 1e9, 1) if p_us > 0 else None,
-                    "bytes_per_slice": p_bytes, "us_per_slice": p_us},
+        "product_tflops": round(g_flops / (g_us * 1e-6) / 1e12, 3),
+        "permute": {"achieved_gbs": round(p_bytes / (p_us * 1e-6) / 1e9, 1) if p_us > 0 else None,
+                    "bytes_per_group": p_bytes, "us_per_group": p_us},
     }
 
 

@@ -102,12 +102,13 @@ typedef struct stem_step_info {
   int32_t n_shared;       /* s: labels summed in this step, K = 2^s */
   int32_t n_free;         /* f: new labels from the branch, N = 2^f */
   int32_t permuted;       /* 1 if a stem permute runs before the product */
-  int32_t reserved;
+  int32_t last_slices;    /* slices covered by the timed launches below (0: none) */
   int64_t M, K, N;        /* product [M x K] . [K x N] -> [M x N], complex */
   double flops;           /* 8 M K N */
   double bytes;           /* 8 (M K + M N + K N): one read of stem and branch, one write */
   double perm_bytes;      /* 16 * 2^rank_in if permuted, else 0 */
-  float last_gemm_us;     /* from the last STEM_TIME_STEPS call, or -1 */
+  float last_gemm_us;     /* product launch of the last STEM_TIME_STEPS call, or -1;
+                             one launch covers last_slices slices */
   float last_perm_us;     /* idem for the permute, or -1 */
 } stem_step_info;
 
@@ -144,9 +145,13 @@ stem_status stem_plan_destroy(stem_plan_t plan);
 
 stem_status stem_plan_summary_get(stem_plan_t plan, stem_plan_summary* summary);
 
-/* Bytes of device workspace stem_contract needs: two stem buffers of the
- * peak size.  The caller allocates it (any 256-byte-aligned device memory). */
-stem_status stem_plan_workspace_bytes(stem_plan_t plan, uint64_t* bytes);
+/* Bytes of device workspace stem_contract needs to keep `slices_in_flight`
+ * slices in flight (1..4096): two stem buffers of the peak size per slice.
+ * The caller allocates it (any 256-byte-aligned device memory);
+ * stem_contract runs as many slices per launch as the workspace it is
+ * given holds. */
+stem_status stem_plan_workspace_bytes(stem_plan_t plan, uint32_t slices_in_flight,
+                                      uint64_t* bytes);
 
 stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* info);
 
@@ -159,11 +164,13 @@ stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* i
  *   out:         device complex128 [n_batch][2^n_open], entry order = the
  *                plan's open_labels (first most significant).  Overwritten
  *                with the sum, or added to with STEM_ACCUMULATE.  Each slice
- *                is added in FP64 in increasing slice order (deterministic).
- * Asynchronous on `stream`; the plan must not be used on two streams at
- * once.  An empty range writes zeros (or adds nothing).  s1 > 2^n_sliced
- * or s0 > s1: STEM_ERANGE.  ws_bytes below stem_plan_workspace_bytes:
- * STEM_ENOMEM.
+ *                is added in FP64 in increasing slice order, one addition
+ *                at a time, whatever the group size (deterministic).
+ * The slices run in groups of as many as the workspace holds, each step of
+ * a group in one kernel launch per kernel.  Asynchronous on `stream`; the
+ * plan must not be used on two streams at once.  An empty range writes
+ * zeros (or adds nothing).  s1 > 2^n_sliced or s0 > s1: STEM_ERANGE.
+ * ws_bytes below stem_plan_workspace_bytes(plan, 1): STEM_ENOMEM.
  */
 stem_status stem_contract(stem_plan_t plan, uint64_t s0, uint64_t s1,
                           const uint64_t* proj_assign, uint32_t n_batch,

@@ -52,7 +52,7 @@ class stem_step_info(ctypes.Structure):
     _fields_ = [
         ("rank_in", ctypes.c_int32), ("rank_out", ctypes.c_int32),
         ("n_shared", ctypes.c_int32), ("n_free", ctypes.c_int32),
-        ("permuted", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("permuted", ctypes.c_int32), ("last_slices", ctypes.c_int32),
         ("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
         ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
         ("perm_bytes", ctypes.c_double),
@@ -78,7 +78,7 @@ SIGNATURES = {
     "stem_plan_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "stem_plan_summary_get": (ctypes.c_int32, [ctypes.c_void_p,
                                                ctypes.POINTER(stem_plan_summary)]),
-    "stem_plan_workspace_bytes": (ctypes.c_int32, [ctypes.c_void_p,
+    "stem_plan_workspace_bytes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32,
                                                    ctypes.POINTER(ctypes.c_uint64)]),
     "stem_step_info_get": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.POINTER(stem_step_info)]),

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,8 +26,7 @@ using namespace stem;
 
 struct StepDev {
   size_t boff = 0;          // offset of variant 0 in the plan's branch buffer (bytes)
-  size_t bstride = 0;       // bytes per variant
-  int eb_base = 0;          // index of variant 0's scale exponent (split paths)
+  size_t bstride = 0;       // bytes per variant block (header + fragments)
 };
 
 struct stem_plan_s {
@@ -37,9 +37,9 @@ struct stem_plan_s {
   uint64_t stem_var_elems = 0;      // complex entries per stem variant
   unsigned char* d_branch = nullptr;
   std::vector<StepDev> sd;
-  std::vector<int> ebs;             // per step and variant: branch scale exponent
   std::vector<hipEvent_t> ev;       // 4 per step when timing: perm start/end, gemm start/end
   std::vector<float> gemm_us, perm_us;
+  int timed_slices = 0;
   bool timed_pending = false;
 };
 
@@ -54,6 +54,35 @@ struct stem_plan_s {
 
 static stem_status fail(stem_status s, const std::string& msg) {
   set_error(msg);
+  return s;
+}
+
+// An operand without per-slice variants: batch item z at ptr + z * zstride.
+static Operand plain_operand(const void* ptr, int64_t zstride) {
+  Operand o;
+  std::memset(&o, 0, sizeof(o));
+  o.ptr = ptr;
+  o.zstride = zstride;
+  return o;
+}
+
+// Variant selection of a tensor's fixed labels (MSB first) for one
+// projected assignment pa: projected bits go into vbase, sliced ones are
+// read from the slice id on the device.
+static SliceSel make_sel(const std::vector<FixedSrc>& src, uint64_t pa, int n_sliced, int n_proj) {
+  SliceSel s;
+  std::memset(&s, 0, sizeof(s));
+  const int nf = (int)src.size();
+  for (int j = 0; j < nf; ++j) {
+    const int vpos = nf - 1 - j;
+    if (src[j].is_proj) {
+      s.vbase |= (uint64_t)fixed_bit(src[j], 0, pa, n_sliced, n_proj) << vpos;
+    } else {
+      s.vshift[s.nv] = (int8_t)(n_sliced - 1 - src[j].index);
+      s.vpos[s.nv] = (int8_t)vpos;
+      s.nv++;
+    }
+  }
   return s;
 }
 
@@ -127,7 +156,7 @@ static stem_status plan_create_impl(const stem_plan_desc* d, hipStream_t st, ste
       src = tmp;
     }
     const PermArgs pa = make_perm(L.stem_labels_in, stem_order);
-    hipError_t e = launch_permute(src, p->d_stem, pa, st);
+    hipError_t e = launch_permute(plain_operand(src, 0), plain_operand(p->d_stem, 0), pa, 0, 1, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return fail(STEM_EHIP, std::string("stem relayout: ") + hipGetErrorString(e));
@@ -144,16 +173,9 @@ static stem_status plan_create_impl(const stem_plan_desc* d, hipStream_t st, ste
   for (size_t i = 0; i < L.steps.size(); ++i) {
     const StepLayout& S = L.steps[i];
     const uint64_t nvar = 1ull << S.fixed.size();
-    size_t per = 0;
-    if (p->precision == STEM_FP32)
-      per = bfrag_f32_floats(S.K, S.N) * 4;
-    else
-      per = bfrag_split_halves(S.K, S.N) * 2 * 2;
-    per = (per + 255) & ~size_t(255);
+    const size_t per = branch_block_bytes(p->precision, S.K, S.N);
     p->sd[i].boff = total;
     p->sd[i].bstride = per;
-    p->sd[i].eb_base = (int)p->ebs.size();
-    p->ebs.resize(p->ebs.size() + nvar, 0);
     total += per * nvar;
   }
   std::vector<unsigned char> hb(std::max<size_t>(total, 256), 0);
@@ -170,14 +192,17 @@ static stem_status plan_create_impl(const stem_plan_desc* d, hipStream_t st, ste
     const uint64_t nvar = 1ull << S.fixed.size();
     const size_t sub = (size_t)(S.K * S.N) * 2;  // floats per variant
     for (uint64_t v = 0; v < nvar; ++v) {
-      unsigned char* dst = hb.data() + p->sd[i].boff + v * p->sd[i].bstride;
+      unsigned char* blk = hb.data() + p->sd[i].boff + v * p->sd[i].bstride;
+      unsigned char* dst = blk + kBranchHeader;
+      float inv_b = 1.f;
       if (p->precision == STEM_FP32) {
         build_bfrag_f32(re.data() + v * sub, S.K, S.N, (float*)dst);
       } else {
-        p->ebs[p->sd[i].eb_base + v] = build_bfrag_split(re.data() + v * sub, S.K, S.N,
-                                                         p->precision == STEM_SPLIT_BF16,
-                                                         (uint16_t*)dst);
+        const int eb = build_bfrag_split(re.data() + v * sub, S.K, S.N,
+                                         p->precision == STEM_SPLIT_BF16, (uint16_t*)dst);
+        inv_b = std::ldexp(1.f, -eb);
       }
+      std::memcpy(blk, &inv_b, sizeof(inv_b));
     }
   }
   HIPCHK(hipMalloc(&p->d_branch, hb.size()));
@@ -221,10 +246,17 @@ stem_status stem_plan_summary_get(stem_plan_t plan, stem_plan_summary* summary) 
   return STEM_OK;
 }
 
-stem_status stem_plan_workspace_bytes(stem_plan_t plan, uint64_t* bytes) {
+static uint64_t slice_ws_bytes(const stem_plan_s* p) {
+  if (p->L.steps.empty()) return 0;
+  return 2 * (((8ull << p->L.max_ws_rank) + 255) & ~255ull);
+}
+
+stem_status stem_plan_workspace_bytes(stem_plan_t plan, uint32_t slices_in_flight,
+                                      uint64_t* bytes) {
   if (!plan || !bytes) return fail(STEM_EINVAL, "null argument");
-  const uint64_t one = plan->L.steps.empty() ? 0 : ((8ull << plan->L.max_ws_rank) + 255) & ~255ull;
-  *bytes = std::max<uint64_t>(2 * one, 256);
+  if (slices_in_flight < 1 || slices_in_flight > (uint32_t)kMaxSlicesInFlight)
+    return fail(STEM_ERANGE, "slices_in_flight outside [1, 4096]");
+  *bytes = std::max<uint64_t>(slice_ws_bytes(plan) * slices_in_flight, 256);
   return STEM_OK;
 }
 
@@ -258,22 +290,9 @@ stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* i
     }
     plan->timed_pending = false;
   }
+  info->last_slices = plan->timed_slices;
   info->last_gemm_us = plan->gemm_us[step];
   info->last_perm_us = plan->perm_us[step];
-  return STEM_OK;
-}
-
-static stem_status run_gemm(stem_plan_s* p, size_t i, uint64_t var, const float* in, float* out,
-                            hipStream_t st) {
-  const StepLayout& S = p->L.steps[i];
-  const unsigned char* b = p->d_branch + p->sd[i].boff + var * p->sd[i].bstride;
-  hipError_t e;
-  if (p->precision == STEM_FP32)
-    e = launch_cgemm_f32(in, (const float*)b, out, S.M, S.K, S.N, S.gemm, st);
-  else
-    e = launch_cgemm_split(in, (const uint16_t*)b, p->ebs[p->sd[i].eb_base + var], out, S.M,
-                           S.K, S.N, p->precision == STEM_SPLIT_BF16, S.gemm, st);
-  if (e != hipSuccess) return fail(STEM_EHIP, std::string("product kernel: ") + hipGetErrorString(e));
   return STEM_OK;
 }
 
@@ -289,13 +308,16 @@ stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_
   if (n_batch == 0) return STEM_OK;
   if (proj_assign)
     for (uint32_t b = 0; b < n_batch; ++b)
-      if (n_pr < 64 && proj_assign[b] >= (1ull << n_pr))
+      if (proj_assign[b] >= (1ull << n_pr))
         return fail(STEM_ERANGE, "projected assignment out of range");
-  uint64_t need = 0;
-  stem_plan_workspace_bytes(p, &need);
-  if (!L.steps.empty() && (!ws || ws_bytes < need))
-    return fail(STEM_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
-                                 std::to_string(need));
+  const uint64_t per = slice_ws_bytes(p);
+  uint64_t group = kMaxSlicesInFlight;
+  if (per) {
+    if (!ws || ws_bytes < per)
+      return fail(STEM_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                   std::to_string(per) + " per slice in flight");
+    group = std::min<uint64_t>(ws_bytes / per, kMaxSlicesInFlight);
+  }
   const uint64_t n_out = 1ull << L.open.size();
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -310,36 +332,49 @@ stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_
     p->ev.resize(4 * L.steps.size());
     for (auto& e : p->ev) HIPCHK(hipEventCreate(&e));
   }
-  const uint64_t half = need / 2;
-  float* buf[2] = {(float*)ws, (float*)((unsigned char*)ws + half)};
+  // the two stem buffers of every slice in flight: [X: group][Y: group]
+  const int64_t half = (int64_t)(per / 2);
+  const int64_t ybase = half * (int64_t)group;
+  unsigned char* wsb = (unsigned char*)ws;
+  std::vector<SliceSel> bsel(L.steps.size());
   for (uint32_t b = 0; b < n_batch; ++b) {
     const uint64_t pa = proj_assign ? proj_assign[b] : 0;
-    for (uint64_t s = s0; s < s1; ++s) {
-      const bool time_this = timing && b + 1 == n_batch && s + 1 == s1;
-      const uint64_t sv = variant_index(L.stem_fixed_src, s, pa, n_sl, n_pr);
-      const float* cur = p->d_stem + 2 * sv * p->stem_var_elems;
+    Operand stem_op = plain_operand(p->d_stem, 0);
+    stem_op.vstride = (int64_t)(8 * p->stem_var_elems);
+    stem_op.sel = make_sel(L.stem_fixed_src, pa, n_sl, n_pr);
+    for (size_t i = 0; i < L.steps.size(); ++i)
+      bsel[i] = make_sel(L.steps[i].fixed_src, pa, n_sl, n_pr);
+    for (uint64_t c0 = s0; c0 < s1; c0 += group) {
+      const int nz = (int)std::min<uint64_t>(group, s1 - c0);
+      const bool time_this = timing && b + 1 == n_batch && c0 + group >= s1;
+      if (time_this) p->timed_slices = nz;
+      Operand cur = stem_op;
       int cur_buf = -1;
       for (size_t i = 0; i < L.steps.size(); ++i) {
         const StepLayout& S = L.steps[i];
         if (S.permuted) {
           const int dst = cur_buf == 0 ? 1 : 0;
+          const Operand o = plain_operand(wsb + (dst ? ybase : 0), half);
           if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i], st));
-          hipError_t e = launch_permute(cur, buf[dst], S.perm, st);
+          hipError_t e = launch_permute(cur, o, S.perm, c0, nz, st);
           if (e != hipSuccess) return fail(STEM_EHIP, std::string("permute: ") + hipGetErrorString(e));
           if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 1], st));
-          cur = buf[dst];
+          cur = o;
           cur_buf = dst;
         }
         const int dst = cur_buf == 0 ? 1 : 0;
-        const uint64_t var = variant_index(S.fixed_src, s, pa, n_sl, n_pr);
+        const Operand o = plain_operand(wsb + (dst ? ybase : 0), half);
+        Operand bop = plain_operand(p->d_branch + p->sd[i].boff, 0);
+        bop.vstride = (int64_t)p->sd[i].bstride;
+        bop.sel = bsel[i];
         if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 2], st));
-        stem_status rs = run_gemm(p, i, var, cur, buf[dst], st);
-        if (rs != STEM_OK) return rs;
+        hipError_t e = launch_cgemm(p->precision, cur, bop, o, c0, nz, S.M, S.K, S.N, S.gemm, st);
+        if (e != hipSuccess) return fail(STEM_EHIP, std::string("product: ") + hipGetErrorString(e));
         if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 3], st));
-        cur = buf[dst];
+        cur = o;
         cur_buf = dst;
       }
-      hipError_t e = launch_acc_f64(cur, out + 2 * n_out * b, L.final_map, st);
+      hipError_t e = launch_acc_f64(cur, c0, nz, out + 2 * n_out * b, L.final_map, st);
       if (e != hipSuccess) return fail(STEM_EHIP, std::string("accumulate: ") + hipGetErrorString(e));
     }
   }

@@ -34,14 +34,20 @@ size_t bfrag_split_halves(int64_t K, int64_t N);  // per part (hi or lo)
 // Writes hi then lo (2 * bfrag_split_halves uint16 values); returns eb.
 int build_bfrag_split(const float* b, int64_t K, int64_t N, int bf16, uint16_t* out);
 
+// Bytes of one branch variant block: a kBranchHeader header (the split
+// paths keep 2^-eb there as a float) and the fragments.
+size_t branch_block_bytes(int precision, int64_t K, int64_t N);
+
 // ---- launchers ---------------------------------------------------------
-hipError_t launch_permute(const float* in, float* out, const PermArgs& p, hipStream_t st);
-hipError_t launch_cgemm_f32(const float* A, const float* Bf, float* C, int64_t M, int64_t K,
-                            int64_t N, const GemmLayout& lay, hipStream_t st);
-hipError_t launch_cgemm_split(const float* A, const uint16_t* Bhl, int eb, float* C,
-                              int64_t M, int64_t K, int64_t N, int bf16, const GemmLayout& lay,
-                              hipStream_t st);
-hipError_t launch_acc_f64(const float* in, double* out, const BitMap& m, hipStream_t st);
+// Every step kernel runs nz slices at once (batch item z = slice s0 + z).
+hipError_t launch_permute(const Operand& in, const Operand& out, const PermArgs& p, uint64_t s0,
+                          int nz, hipStream_t st);
+hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const Operand& C,
+                        uint64_t s0, int nz, int64_t M, int64_t K, int64_t N,
+                        const GemmLayout& lay, hipStream_t st);
+// out[o] += sum over z < nz (in order) of in_z[i], o = i re-ordered by m.
+hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, const BitMap& m,
+                          hipStream_t st);
 hipError_t launch_zero_f64(double* p, uint64_t n, hipStream_t st);
 hipError_t launch_fill_counter(float* dst, uint64_t n, uint64_t seed, int scale_log2,
                                hipStream_t st);

@@ -1,10 +1,11 @@
 // Device kernels of libstemgpu for gfx950 (CDNA4, wave64).
 //
 // One stem step (paper §A.1, pairwise contraction; §A.2, the stem absorbs a
-// branch) is a bit permutation of the stem's address (only when the summed
-// labels are not already its fastest-varying ones) followed by a complex
-// matrix product [M x K] . [K x N] on the matrix cores.  The sum over slices
-// (§A.1, slicing) is accumulated in FP64.
+// branch) is an optional bit permutation of the stem's address followed by
+// a complex matrix product [M x K] . [K x N] on the matrix cores.  The sum
+// over slices (§A.1, slicing) is accumulated in FP64.  Every step kernel
+// handles a batch of slices at once: blockIdx.z is the batch item, and each
+// operand finds its slice's sub-tensor from the slice id (Operand).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -22,6 +23,21 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
+constexpr int kLdsBudget = 64 * 1024;  // branch fragments staged in LDS up to this size
+constexpr int kTargetBlocks = 4096;    // workgroups per launch before row loops kick in
+
+// Loops over the small per-launch tables below are fully unrolled with a
+// predicate, so every table index is a constant and the tables stay in
+// scalar registers instead of being copied into per-lane arrays.
+__device__ __forceinline__ const char* op_base(const Operand& o, int z, uint64_t s0) {
+  uint64_t v = o.sel.vbase;
+  const uint64_t s = s0 + (uint64_t)z;
+#pragma unroll
+  for (int j = 0; j < kMaxSlicedPerTensor; ++j)
+    if (j < o.sel.nv) v |= ((s >> o.sel.vshift[j]) & 1ull) << o.sel.vpos[j];
+  return (const char*)o.ptr + (int64_t)z * o.zstride + (int64_t)v * o.vstride;
+}
+
 // ---------------------------------------------------------------------------
 // Bit-permutation transpose, staged through LDS.
 //
@@ -32,10 +48,12 @@ typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 // bits are also tile bits, so the writes are contiguous runs too.  One
 // padding entry per 32 keeps the strided LDS reads off a single bank.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void stem_permute_kernel(const float2* __restrict__ in,
-                                                           float2* __restrict__ out,
-                                                           PermArgs p) {
+__global__ __launch_bounds__(256) void stem_permute_kernel(Operand in_op, Operand out_op,
+                                                           uint64_t s0, PermArgs p) {
   __shared__ float2 tile[(1 << kPermTileMaxBits) + (1 << kPermTileMaxBits) / 32];
+  const int z = blockIdx.z;
+  const float2* __restrict__ in = (const float2*)op_base(in_op, z, s0);
+  float2* __restrict__ out = (float2*)op_base(out_op, z, s0);
   const uint64_t w = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
   uint64_t ib = 0, ob = 0;
   for (int i = 0; i < p.nn; ++i) {
@@ -62,12 +80,13 @@ __global__ __launch_bounds__(256) void stem_permute_kernel(const float2* __restr
   }
 }
 
-hipError_t launch_permute(const float* in, float* out, const PermArgs& p, hipStream_t st) {
+hipError_t launch_permute(const Operand& in, const Operand& out, const PermArgs& p, uint64_t s0,
+                          int nz, hipStream_t st) {
   const uint64_t blocks = 1ull << p.nn;
   const uint64_t gx = std::min<uint64_t>(blocks, 1ull << 20);
   const uint64_t gy = blocks / gx;
-  hipLaunchKernelGGL(stem_permute_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st,
-                     (const float2*)in, (float2*)out, p);
+  hipLaunchKernelGGL(stem_permute_kernel, dim3((unsigned)gx, (unsigned)gy, (unsigned)nz),
+                     dim3(256), 0, st, in, out, s0, p);
   return hipGetLastError();
 }
 
@@ -91,16 +110,21 @@ hipError_t launch_permute(const float* in, float* out, const PermArgs& p, hipStr
 
 __device__ __forceinline__ int64_t spread_rows(int64_t m, const GemmGeom& g) {
   int64_t a = m;
-  for (int i = 0; i < g.s; ++i) {
-    const int p = g.sins[i];
-    a = ((a >> p) << (p + 1)) | (a & ((1ll << p) - 1));
+#pragma unroll
+  for (int i = 0; i < kMaxShared; ++i) {
+    if (i < g.s) {
+      const int p = g.sins[i];
+      a = ((a >> p) << (p + 1)) | (a & ((1ll << p) - 1));
+    }
   }
   return a;
 }
 
 __device__ __forceinline__ int64_t k_offset(int k, const GemmGeom& g) {
   int64_t a = 0;
-  for (int i = 0; i < g.s; ++i) a |= (int64_t)((k >> i) & 1) << g.spos[i];
+#pragma unroll
+  for (int i = 0; i < kMaxShared; ++i)
+    if (i < g.s) a |= (int64_t)((k >> i) & 1) << g.spos[i];
   return a;
 }
 
@@ -115,6 +139,7 @@ template <int AM>
 __device__ __forceinline__ f32x4 load_kr4(const float* __restrict__ A, int64_t rb, int kr0,
                                           int64_t ko0, int64_t ko1, const GemmGeom& g) {
   f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (rb < 0) return v;
   if (AM == 0) {
     if (kr0 < g.Kr) {
       const float* src = A + 2 * rb + kr0;
@@ -173,72 +198,114 @@ __device__ __forceinline__ void store_nr4(float* __restrict__ C, int64_t m, int 
 // A[m][16 kc + 4 g .. +3] and feeds element j to MFMA number j; the branch
 // fragments were laid out on the host in the same k order.
 //
-// Each wave handles TM 16-row blocks (so every branch fragment is reused TM
-// times) and NTW 16-column tiles; blockIdx.y splits wide outputs.
+// Each wave handles TM 16-row blocks (every branch fragment is reused TM
+// times) and NTW 16-column tiles; blockIdx.y splits wide outputs.  With
+// BLDS the workgroup first copies its branch fragments into LDS; the
+// workgroups then loop over the row blocks.
 // ---------------------------------------------------------------------------
-template <int TM, int NTW, int AM, int CM>
-__global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(const float* __restrict__ A,
-                                                             const float* __restrict__ Bf,
-                                                             float* __restrict__ C, GemmGeom g) {
+template <int TM, int NTW, int AM, int CM, int BLDS>
+__global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand Bo, Operand Co,
+                                                             uint64_t s0, GemmGeom g) {
+  extern __shared__ __align__(16) float sB[];
+  const int z = blockIdx.z;
+  const float* __restrict__ A = (const float*)op_base(Ao, z, s0);
+  const float* __restrict__ Bf = (const float*)(op_base(Bo, z, s0) + kBranchHeader);
+  float* __restrict__ C = (float*)op_base(Co, z, s0);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int grp = lane >> 4;
   const int r16 = lane & 15;
   const int nt0 = blockIdx.y * NTW;
   const int ntw = min(NTW, g.NT - nt0);
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * TM);
-  if (row0 >= g.M) return;
 
-  f32x4 acc[TM][NTW];
-  int64_t rb[TM];
-#pragma unroll
-  for (int t = 0; t < TM; ++t) {
-    const int64_t row = row0 + t * 16 + r16;
-    rb[t] = row < g.M ? row_base<AM>(row, g) : -1;
-#pragma unroll
-    for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (BLDS) {
+    const int per_kc = ntw * 256;
+    for (int i = threadIdx.x * 4; i < g.KC * per_kc; i += 1024) {
+      const int kc = i / per_kc, r = i - kc * per_kc;
+      *(f32x4*)(sB + kc * NTW * 256 + r) = *(const f32x4*)(Bf + (size_t)(kc * g.NT + nt0) * 256 + r);
+    }
+    __syncthreads();
   }
 
-  for (int kc = 0; kc < g.KC; ++kc) {
-    const int kr0 = kc * 16 + grp * 4;
-    int64_t ko0 = 0, ko1 = 0;
-    if (AM == 1) {
-      ko0 = k_offset(kr0 >> 1, g);
-      ko1 = k_offset((kr0 >> 1) + 1, g);
+  const int64_t rows_per_wg = 4 * 16 * TM;
+  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    if (row0 >= g.M) continue;
+    f32x4 acc[TM][NTW];
+    int64_t rb[TM];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t row = row0 + t * 16 + r16;
+      rb[t] = row < g.M ? row_base<AM>(row, g) : -1;
+#pragma unroll
+      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     f32x4 a[TM];
+    {
+      const int kr0 = grp * 4;
+      const int64_t ko0 = AM == 1 ? k_offset(kr0 >> 1, g) : 0;
+      const int64_t ko1 = AM == 1 ? k_offset((kr0 >> 1) + 1, g) : 0;
 #pragma unroll
-    for (int t = 0; t < TM; ++t)
-      a[t] = rb[t] >= 0 ? load_kr4<AM>(A, rb[t], kr0, ko0, ko1, g) : f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < TM; ++t) a[t] = load_kr4<AM>(A, rb[t], kr0, ko0, ko1, g);
+    }
+    for (int kc = 0; kc < g.KC; ++kc) {
+      // prefetch the next k chunk of A while this one is multiplied
+      f32x4 an[TM];
+      if (kc + 1 < g.KC) {
+        const int kr1 = (kc + 1) * 16 + grp * 4;
+        const int64_t ko0 = AM == 1 ? k_offset(kr1 >> 1, g) : 0;
+        const int64_t ko1 = AM == 1 ? k_offset((kr1 >> 1) + 1, g) : 0;
 #pragma unroll
-    for (int n = 0; n < NTW; ++n) {
-      if (n < ntw) {
-        const float* bp = Bf + ((size_t)(kc * g.NT + nt0 + n) * 4) * 64 + lane;
-        const float b0 = bp[0], b1 = bp[64], b2 = bp[128], b3 = bp[192];
+        for (int t = 0; t < TM; ++t) an[t] = load_kr4<AM>(A, rb[t], kr1, ko0, ko1, g);
+      }
 #pragma unroll
-        for (int t = 0; t < TM; ++t) {
-          acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a[t].x, acc[t][n], 0, 0, 0);
-          acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a[t].y, acc[t][n], 0, 0, 0);
-          acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b2, a[t].z, acc[t][n], 0, 0, 0);
-          acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b3, a[t].w, acc[t][n], 0, 0, 0);
+      for (int n = 0; n < NTW; ++n) {
+        if (n < ntw) {
+          float b[4];
+          if (BLDS) {
+            const float* bp = sB + (kc * NTW + n) * 256 + lane;
+            b[0] = bp[0]; b[1] = bp[64]; b[2] = bp[128]; b[3] = bp[192];
+          } else {
+            const float* bp = Bf + ((size_t)(kc * g.NT + nt0 + n) * 4) * 64 + lane;
+            b[0] = bp[0]; b[1] = bp[64]; b[2] = bp[128]; b[3] = bp[192];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int t = 0; t < TM; ++t)
+              acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[t][j], acc[t][n], 0, 0, 0);
         }
       }
+      if (kc + 1 < g.KC) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t) a[t] = an[t];
+      }
     }
-  }
-
 #pragma unroll
-  for (int t = 0; t < TM; ++t) {
-    const int64_t row = row0 + t * 16 + r16;
-    if (row >= g.M) continue;
+    for (int t = 0; t < TM; ++t) {
+      const int64_t row = row0 + t * 16 + r16;
+      if (row >= g.M) continue;
 #pragma unroll
-    for (int n = 0; n < NTW; ++n)
-      if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n], g);
+      for (int n = 0; n < NTW; ++n)
+        if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n], g);
+    }
   }
 }
 
 size_t bfrag_f32_floats(int64_t K, int64_t N) {
   const int64_t Kp = std::max<int64_t>(16, 2 * K), Np = std::max<int64_t>(16, 2 * N);
   return (size_t)(Kp * Np);
+}
+
+size_t bfrag_split_halves(int64_t K, int64_t N) {
+  const int64_t Kq = std::max<int64_t>(32, 2 * K), Np = std::max<int64_t>(16, 2 * N);
+  return (size_t)(Kq * Np);
+}
+
+size_t branch_block_bytes(int precision, int64_t K, int64_t N) {
+  size_t body = precision == STEM_FP32 ? bfrag_f32_floats(K, N) * 4 : bfrag_split_halves(K, N) * 4;
+  return (kBranchHeader + body + 255) & ~size_t(255);
 }
 
 // Expanded real entry B'[kr][nr] of a complex [K x N] matrix b (interleaved).
@@ -283,41 +350,41 @@ static GemmGeom make_geom(const GemmLayout& lay, int64_t M, int64_t K, int64_t N
   return g;
 }
 
-template <int TM, int NTW, int AM, int CM>
-static void launch_f32_t(const float* A, const float* Bf, float* C, const GemmGeom& g,
-                         hipStream_t st) {
-  const int64_t rows_per_block = 4 * 16 * TM;
-  const int64_t gx = (g.M + rows_per_block - 1) / rows_per_block;
+// Grid of a product launch: x row-block groups (each workgroup loops over
+// row blocks when there are more than the target), y column chunks, z slices.
+static dim3 gemm_grid(const GemmGeom& g, int TM, int NTW, int nz) {
+  const int64_t rows_per_wg = 4 * 16 * TM;
+  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
   const int gy = (g.NT + NTW - 1) / NTW;
-  hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM>), dim3((unsigned)gx, (unsigned)gy),
-                     dim3(256), 0, st, A, Bf, C, g);
+  const int64_t want = std::max<int64_t>(1, kTargetBlocks / ((int64_t)gy * nz));
+  const int64_t gx = std::min<int64_t>(nblk, want);
+  return dim3((unsigned)gx, (unsigned)gy, (unsigned)nz);
+}
+
+template <int TM, int NTW, int AM, int CM>
+static void launch_f32_t(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
+                         int nz, const GemmGeom& g, hipStream_t st) {
+  const dim3 grid = gemm_grid(g, TM, NTW, nz);
+  const size_t lds = (size_t)g.KC * NTW * 256 * 4;
+  if (lds <= (size_t)kLdsBudget)
+    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1>), grid, dim3(256), lds, st, A,
+                       B, C, s0, g);
+  else
+    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 0>), grid, dim3(256), 0, st, A, B,
+                       C, s0, g);
 }
 
 template <int AM, int CM>
-static void launch_f32_m(const float* A, const float* Bf, float* C, const GemmGeom& g,
-                         hipStream_t st) {
+static void launch_f32_m(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
+                         int nz, const GemmGeom& g, hipStream_t st) {
   if (g.NT <= 1)
-    launch_f32_t<4, 1, AM, CM>(A, Bf, C, g, st);
+    launch_f32_t<4, 1, AM, CM>(A, B, C, s0, nz, g, st);
   else if (g.NT <= 2)
-    launch_f32_t<4, 2, AM, CM>(A, Bf, C, g, st);
+    launch_f32_t<4, 2, AM, CM>(A, B, C, s0, nz, g, st);
   else if (g.NT <= 4)
-    launch_f32_t<4, 4, AM, CM>(A, Bf, C, g, st);
+    launch_f32_t<2, 4, AM, CM>(A, B, C, s0, nz, g, st);
   else
-    launch_f32_t<4, 8, AM, CM>(A, Bf, C, g, st);
-}
-
-hipError_t launch_cgemm_f32(const float* A, const float* Bf, float* C, int64_t M, int64_t K,
-                            int64_t N, const GemmLayout& lay, hipStream_t st) {
-  const GemmGeom g = make_geom(lay, M, K, N, 16);
-  if (lay.amode == 0 && lay.cmode == 0)
-    launch_f32_m<0, 0>(A, Bf, C, g, st);
-  else if (lay.amode == 0)
-    launch_f32_m<0, 1>(A, Bf, C, g, st);
-  else if (lay.cmode == 0)
-    launch_f32_m<1, 0>(A, Bf, C, g, st);
-  else
-    launch_f32_m<1, 1>(A, Bf, C, g, st);
-  return hipGetLastError();
+    launch_f32_t<2, 8, AM, CM>(A, B, C, s0, nz, g, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,8 +398,8 @@ hipError_t launch_cgemm_f32(const float* A, const float* Bf, float* C, int64_t M
 // largest entry lands in [2^13, 2^14); the chunk's partial product is then
 // scaled back by 2^-e before it joins the FP32 accumulator.  BF16 has
 // FP32's range and uses e = 0.  The branch was split and scaled (2^eb) on
-// the host.  Lane layout as in the FP32 kernel with 8 consecutive reals of
-// k per lane group.
+// the host; 2^-eb sits in the variant's header.  Lane layout as in the FP32
+// kernel with 8 consecutive reals of k per lane group.
 // ---------------------------------------------------------------------------
 template <int BF16>
 struct SplitT;
@@ -365,111 +432,131 @@ struct SplitT<1> {
   }
 };
 
-template <int TM, int NTW, int BF16, int AM, int CM>
-__global__ __launch_bounds__(256) void stem_cgemm_split_kernel(const float* __restrict__ A,
-                                                               const uint16_t* __restrict__ Bh,
-                                                               const uint16_t* __restrict__ Bl,
-                                                               float* __restrict__ C,
-                                                               GemmGeom g, float inv_b) {
+template <int TM, int NTW, int BF16, int AM, int CM, int BLDS>
+__global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Operand Bo,
+                                                               Operand Co, uint64_t s0,
+                                                               GemmGeom g) {
   typedef SplitT<BF16> S;
   typedef typename S::vec vec;
+  extern __shared__ __align__(16) uint16_t sBh[];
+  const int z = blockIdx.z;
+  const float* __restrict__ A = (const float*)op_base(Ao, z, s0);
+  const char* bblock = op_base(Bo, z, s0);
+  const float inv_b = *(const float*)bblock;
+  const uint16_t* __restrict__ Bh = (const uint16_t*)(bblock + kBranchHeader);
+  const size_t part = (size_t)g.KC * g.NT * 512;  // halves per part (hi or lo)
+  const uint16_t* __restrict__ Bl = Bh + part;
+  float* __restrict__ C = (float*)op_base(Co, z, s0);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int grp = lane >> 4;
   const int r16 = lane & 15;
   const int nt0 = blockIdx.y * NTW;
   const int ntw = min(NTW, g.NT - nt0);
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * TM);
-  if (row0 >= g.M) return;
+  uint16_t* sBl = sBh + (size_t)g.KC * NTW * 512;
 
-  f32x4 acc[TM][NTW];
-  int64_t rb[TM];
-#pragma unroll
-  for (int t = 0; t < TM; ++t) {
-    const int64_t row = row0 + t * 16 + r16;
-    rb[t] = row < g.M ? row_base<AM>(row, g) : -1;
-#pragma unroll
-    for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (BLDS) {
+    const int per_kc = ntw * 512;  // halves of one part per k chunk
+    for (int i = threadIdx.x * 8; i < g.KC * per_kc; i += 2048) {
+      const int kc = i / per_kc, r = i - kc * per_kc;
+      const size_t src = (size_t)(kc * g.NT + nt0) * 512 + r;
+      *(u16x8*)(sBh + kc * NTW * 512 + r) = *(const u16x8*)(Bh + src);
+      *(u16x8*)(sBl + kc * NTW * 512 + r) = *(const u16x8*)(Bl + src);
+    }
+    __syncthreads();
   }
 
-  for (int kc = 0; kc < g.KC; ++kc) {
-    const int kr0 = kc * 32 + grp * 8;
-    int64_t ko[4] = {0, 0, 0, 0};
-    if (AM == 1) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) ko[i] = k_offset((kr0 >> 1) + i, g);
-    }
-    u16x8 ahi[TM], alo[TM];
-    float inv_a[TM];
+  const int64_t rows_per_wg = 4 * 16 * TM;
+  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    if (row0 >= g.M) continue;
+    f32x4 acc[TM][NTW];
+    int64_t rb[TM];
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-      f32x4 x0 = f32x4{0.f, 0.f, 0.f, 0.f}, x1 = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (rb[t] >= 0) {
-        x0 = load_kr4<AM>(A, rb[t], kr0, ko[0], ko[1], g);
-        x1 = load_kr4<AM>(A, rb[t], kr0 + 4, ko[2], ko[3], g);
-      }
-      const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-      float scale = 1.f;
-      inv_a[t] = 1.f;
-      if (!BF16) {
-        float mx = 0.f;
+      const int64_t row = row0 + t * 16 + r16;
+      rb[t] = row < g.M ? row_base<AM>(row, g) : -1;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(x[i]));
-        mx = fmaxf(mx, __shfl_xor(mx, 16));
-        mx = fmaxf(mx, __shfl_xor(mx, 32));
-        if (mx > 0.f) {
-          int ex;
-          frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
-          const int e = 14 - ex;
-          scale = ldexpf(1.f, e);
-          inv_a[t] = ldexpf(1.f, -e);
+      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int kc = 0; kc < g.KC; ++kc) {
+      const int kr0 = kc * 32 + grp * 8;
+      int64_t ko[4] = {0, 0, 0, 0};
+      if (AM == 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ko[i] = k_offset((kr0 >> 1) + i, g);
+      }
+      vec ahi[TM], alo[TM];
+      float inv_a[TM];
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const f32x4 x0 = load_kr4<AM>(A, rb[t], kr0, ko[0], ko[1], g);
+        const f32x4 x1 = load_kr4<AM>(A, rb[t], kr0 + 4, ko[2], ko[3], g);
+        const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        float scale = 1.f;
+        inv_a[t] = 1.f;
+        if (!BF16) {
+          float mx = 0.f;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(x[i]));
+          mx = fmaxf(mx, __shfl_xor(mx, 16));
+          mx = fmaxf(mx, __shfl_xor(mx, 32));
+          if (mx > 0.f) {
+            int ex;
+            frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
+            scale = ldexpf(1.f, 14 - ex);
+            inv_a[t] = ldexpf(1.f, ex - 14);
+          }
         }
+        u16x8 h, l;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float xs = x[i] * scale;
+          float back, dummy;
+          h[i] = S::cvt(xs, &back);
+          l[i] = S::cvt(xs - back, &dummy);
+        }
+        __builtin_memcpy(&ahi[t], &h, 16);
+        __builtin_memcpy(&alo[t], &l, 16);
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float xs = x[i] * scale;
-        float back, dummy;
-        ahi[t][i] = S::cvt(xs, &back);
-        alo[t][i] = S::cvt(xs - back, &dummy);
+      for (int n = 0; n < NTW; ++n) {
+        if (n < ntw) {
+          u16x8 bh, bl;
+          if (BLDS) {
+            const size_t fo = ((size_t)(kc * NTW + n) * 64 + lane) * 8;
+            bh = *(const u16x8*)(sBh + fo);
+            bl = *(const u16x8*)(sBl + fo);
+          } else {
+            const size_t fo = ((size_t)(kc * g.NT + nt0 + n) * 64 + lane) * 8;
+            bh = *(const u16x8*)(Bh + fo);
+            bl = *(const u16x8*)(Bl + fo);
+          }
+          vec vbh, vbl;
+          __builtin_memcpy(&vbh, &bh, 16);
+          __builtin_memcpy(&vbl, &bl, 16);
+          f32x4 part3[TM];
+#pragma unroll
+          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, ahi[t], f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbl, ahi[t], part3[t]);
+#pragma unroll
+          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, alo[t], part3[t]);
+#pragma unroll
+          for (int t = 0; t < TM; ++t) acc[t][n] += part3[t] * inv_a[t];
+        }
       }
     }
 #pragma unroll
-    for (int n = 0; n < NTW; ++n) {
-      if (n < ntw) {
-        const size_t fo = ((size_t)(kc * g.NT + nt0 + n) * 64 + lane) * 8;
-        const u16x8 bh = *(const u16x8*)(Bh + fo);
-        const u16x8 bl = *(const u16x8*)(Bl + fo);
-        vec vbh, vbl;
-        __builtin_memcpy(&vbh, &bh, 16);
-        __builtin_memcpy(&vbl, &bl, 16);
+    for (int t = 0; t < TM; ++t) {
+      const int64_t row = row0 + t * 16 + r16;
+      if (row >= g.M) continue;
 #pragma unroll
-        for (int t = 0; t < TM; ++t) {
-          vec vah, val;
-          __builtin_memcpy(&vah, &ahi[t], 16);
-          __builtin_memcpy(&val, &alo[t], 16);
-          f32x4 part = f32x4{0.f, 0.f, 0.f, 0.f};
-          part = S::mfma(vbh, vah, part);
-          part = S::mfma(vbl, vah, part);
-          part = S::mfma(vbh, val, part);
-          acc[t][n] += part * inv_a[t];
-        }
-      }
+      for (int n = 0; n < NTW; ++n)
+        if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n] * inv_b, g);
     }
   }
-
-#pragma unroll
-  for (int t = 0; t < TM; ++t) {
-    const int64_t row = row0 + t * 16 + r16;
-    if (row >= g.M) continue;
-#pragma unroll
-    for (int n = 0; n < NTW; ++n)
-      if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n] * inv_b, g);
-  }
-}
-
-size_t bfrag_split_halves(int64_t K, int64_t N) {
-  const int64_t Kq = std::max<int64_t>(32, 2 * K), Np = std::max<int64_t>(16, 2 * N);
-  return (size_t)(Kq * Np);
 }
 
 static uint16_t host_f16(float x, float* back) {
@@ -526,80 +613,96 @@ int build_bfrag_split(const float* b, int64_t K, int64_t N, int bf16, uint16_t* 
 }
 
 template <int TM, int NTW, int BF16, int AM, int CM>
-static void launch_split_t(const float* A, const uint16_t* Bhl, size_t part, float inv_b,
-                           float* C, const GemmGeom& g, hipStream_t st) {
-  const int64_t rows_per_block = 4 * 16 * TM;
-  const int64_t gx = (g.M + rows_per_block - 1) / rows_per_block;
-  const int gy = (g.NT + NTW - 1) / NTW;
-  hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM>),
-                     dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, A, Bhl, Bhl + part, C,
-                     g, inv_b);
+static void launch_split_t(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
+                           int nz, const GemmGeom& g, hipStream_t st) {
+  const dim3 grid = gemm_grid(g, TM, NTW, nz);
+  const size_t lds = (size_t)g.KC * NTW * 512 * 2 * 2;
+  if (lds <= (size_t)kLdsBudget)
+    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1>), grid, dim3(256), lds,
+                       st, A, B, C, s0, g);
+  else
+    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 0>), grid, dim3(256), 0,
+                       st, A, B, C, s0, g);
 }
 
 template <int BF16, int AM, int CM>
-static void launch_split_n(const float* A, const uint16_t* Bhl, size_t part, float inv_b,
-                           float* C, const GemmGeom& g, hipStream_t st) {
+static void launch_split_n(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
+                           int nz, const GemmGeom& g, hipStream_t st) {
   if (g.NT <= 1)
-    launch_split_t<4, 1, BF16, AM, CM>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_t<4, 1, BF16, AM, CM>(A, B, C, s0, nz, g, st);
   else if (g.NT <= 2)
-    launch_split_t<4, 2, BF16, AM, CM>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_t<4, 2, BF16, AM, CM>(A, B, C, s0, nz, g, st);
   else if (g.NT <= 4)
-    launch_split_t<4, 4, BF16, AM, CM>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_t<2, 4, BF16, AM, CM>(A, B, C, s0, nz, g, st);
   else
-    launch_split_t<4, 8, BF16, AM, CM>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_t<2, 8, BF16, AM, CM>(A, B, C, s0, nz, g, st);
 }
 
 template <int BF16>
-static void launch_split_b(const float* A, const uint16_t* Bhl, size_t part, float inv_b,
-                           float* C, const GemmGeom& g, const GemmLayout& lay, hipStream_t st) {
+static void launch_split_b(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
+                           int nz, const GemmGeom& g, const GemmLayout& lay, hipStream_t st) {
   if (lay.amode == 0 && lay.cmode == 0)
-    launch_split_n<BF16, 0, 0>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_n<BF16, 0, 0>(A, B, C, s0, nz, g, st);
   else if (lay.amode == 0)
-    launch_split_n<BF16, 0, 1>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_n<BF16, 0, 1>(A, B, C, s0, nz, g, st);
   else if (lay.cmode == 0)
-    launch_split_n<BF16, 1, 0>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_n<BF16, 1, 0>(A, B, C, s0, nz, g, st);
   else
-    launch_split_n<BF16, 1, 1>(A, Bhl, part, inv_b, C, g, st);
+    launch_split_n<BF16, 1, 1>(A, B, C, s0, nz, g, st);
 }
 
-hipError_t launch_cgemm_split(const float* A, const uint16_t* Bhl, int eb, float* C,
-                              int64_t M, int64_t K, int64_t N, int bf16, const GemmLayout& lay,
-                              hipStream_t st) {
-  const GemmGeom g = make_geom(lay, M, K, N, 32);
-  const size_t part = bfrag_split_halves(K, N);
-  const float inv_b = std::ldexp(1.f, -eb);
-  if (bf16)
-    launch_split_b<1>(A, Bhl, part, inv_b, C, g, lay, st);
-  else
-    launch_split_b<0>(A, Bhl, part, inv_b, C, g, lay, st);
+hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const Operand& C,
+                        uint64_t s0, int nz, int64_t M, int64_t K, int64_t N,
+                        const GemmLayout& lay, hipStream_t st) {
+  if (precision == STEM_FP32) {
+    const GemmGeom g = make_geom(lay, M, K, N, 16);
+    if (lay.amode == 0 && lay.cmode == 0)
+      launch_f32_m<0, 0>(A, B, C, s0, nz, g, st);
+    else if (lay.amode == 0)
+      launch_f32_m<0, 1>(A, B, C, s0, nz, g, st);
+    else if (lay.cmode == 0)
+      launch_f32_m<1, 0>(A, B, C, s0, nz, g, st);
+    else
+      launch_f32_m<1, 1>(A, B, C, s0, nz, g, st);
+  } else {
+    const GemmGeom g = make_geom(lay, M, K, N, 32);
+    if (precision == STEM_SPLIT_BF16)
+      launch_split_b<1>(A, B, C, s0, nz, g, lay, st);
+    else
+      launch_split_b<0>(A, B, C, s0, nz, g, lay, st);
+  }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// FP64 accumulation of one slice's final stem into the result (paper §A.1:
-// the value is the sum of the sliced sub-network values), reordered from the
-// stem's final label order into the open-label order.  One thread per entry,
-// so every output entry is added in slice order: deterministic.
+// FP64 accumulation of a batch of slices' final stems into the result
+// (paper §A.1: the value is the sum of the sliced sub-network values),
+// reordered from the stem's final label order into the open-label order.
+// One thread per entry adds the batch items in increasing slice order, so
+// the sum is deterministic.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void stem_acc_f64_kernel(const float2* __restrict__ in,
+__global__ __launch_bounds__(256) void stem_acc_f64_kernel(Operand in_op, uint64_t s0, int nz,
                                                            double2* __restrict__ out, BitMap m,
                                                            uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint64_t o = 0;
   for (int q = 0; q < m.rank; ++q) o |= ((i >> q) & 1ull) << m.dst[q];
-  const float2 v = in[i];
   double2 r = out[o];
-  r.x += (double)v.x;
-  r.y += (double)v.y;
+  for (int z = 0; z < nz; ++z) {
+    const float2 v = ((const float2*)op_base(in_op, z, s0))[i];
+    r.x += (double)v.x;
+    r.y += (double)v.y;
+  }
   out[o] = r;
 }
 
-hipError_t launch_acc_f64(const float* in, double* out, const BitMap& m, hipStream_t st) {
+hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, const BitMap& m,
+                          hipStream_t st) {
   const uint64_t n = 1ull << m.rank;
   const uint64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(stem_acc_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
-                     (const float2*)in, (double2*)out, m, n);
+  hipLaunchKernelGGL(stem_acc_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, in, s0, nz,
+                     (double2*)out, m, n);
   return hipGetLastError();
 }
 

@@ -227,6 +227,15 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     }
   }
   std::vector<int32_t> cur = L->stem_rest;
+  auto too_many_fixed = [](const std::vector<FixedSrc>& src) {
+    int n_sl = 0;
+    for (const FixedSrc& f : src) n_sl += f.is_proj ? 0 : 1;
+    return n_sl > kMaxSlicedPerTensor || src.size() > 62;
+  };
+  if (too_many_fixed(L->stem_fixed_src)) {
+    *err = "the initial stem carries more than 32 sliced or 62 fixed labels";
+    return STEM_EUNSUPPORTED;
+  }
   if ((int)cur.size() > L->max_rank) {
     *err = "initial stem rank " + std::to_string(cur.size()) + " above max_rank " +
            std::to_string(L->max_rank);
@@ -274,6 +283,10 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
       } else {
         rest_b.push_back(x);
       }
+    }
+    if (too_many_fixed(st.fixed_src)) {
+      *err = "branch " + std::to_string(i) + " carries more than 32 sliced labels";
+      return STEM_EUNSUPPORTED;
     }
     std::set<int32_t> rest_set(rest_b.begin(), rest_b.end());
     std::set<int32_t> cur_set(cur.begin(), cur.end());

@@ -59,6 +59,30 @@ struct GemmGeom {
 
 constexpr int kMaxShared = 16;  // K <= 2^16
 constexpr int kMaxFree = 16;    // N <= 2^16
+constexpr int kMaxSlicedPerTensor = 32;
+constexpr int kMaxSlicesInFlight = 4096;
+constexpr int kBranchHeader = 256;  // bytes before each branch variant's fragments
+
+// Selection of one slice's sub-tensor: the variant index (the values of the
+// tensor's fixed labels, most significant first) is vbase (bits fixed by
+// the projected assignment) plus, for each sliced label j, bit vshift[j] of
+// the slice id placed at variant bit vpos[j].
+struct SliceSel {
+  uint64_t vbase;
+  int32_t nv;
+  int32_t pad;
+  int8_t vshift[kMaxSlicedPerTensor];
+  int8_t vpos[kMaxSlicedPerTensor];
+};
+
+// A kernel operand for a batch of slices: batch item z (slice s0 + z)
+// starts at ptr + z * zstride + variant(s0 + z) * vstride (bytes).
+struct Operand {
+  const void* ptr;
+  int64_t zstride;
+  int64_t vstride;
+  SliceSel sel;
+};
 
 // Where the value of a fixed (sliced or projected) label comes from.
 struct FixedSrc {

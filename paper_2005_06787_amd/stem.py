@@ -127,10 +127,16 @@ class Plan:
         C.check(C.lib().stem_plan_summary_get(self._h, ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in s._fields_}
 
-    def workspace_bytes(self) -> int:
+    def workspace_bytes(self, slices_in_flight: int = 1) -> int:
         b = ctypes.c_uint64()
-        C.check(C.lib().stem_plan_workspace_bytes(self._h, ctypes.byref(b)))
+        C.check(C.lib().stem_plan_workspace_bytes(self._h, int(slices_in_flight),
+                                                  ctypes.byref(b)))
         return int(b.value)
+
+    def default_slices_in_flight(self, n_slices: int) -> int:
+        """Slices per launch: all of them, up to 256 and a 16 GiB workspace."""
+        per = max(1, self.workspace_bytes(1))
+        return int(max(1, min(n_slices, 256, (16 << 30) // per)))
 
     def step_info(self, i: int) -> dict:
         s = C.stem_step_info()
@@ -141,22 +147,29 @@ class Plan:
         return [self.step_info(i) for i in range(self.summary()["n_steps"])]
 
     # -- work -------------------------------------------------------------
-    def workspace(self):
+    def workspace(self, slices_in_flight: int = 1):
+        """Device workspace (cached on the plan) for that many slices per launch."""
         torch = self._torch
-        need = self.workspace_bytes()
-        if self._ws is None or self._ws.numel() < need:
+        need = self.workspace_bytes(slices_in_flight)
+        if self._ws is None or self._ws.numel() != need:
+            self._ws = None
             self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
         return self._ws
 
     def contract(self, s0: int = 0, s1: int | None = None, proj=None, out=None,
-                 accumulate: bool = False, time_steps: bool = False, stream=None):
+                 accumulate: bool = False, time_steps: bool = False, stream=None,
+                 slices_in_flight: int | None = None):
         """Sum of slices [s0, s1) for each projected assignment in ``proj``.
 
         Returns (or fills) a complex128 CUDA tensor [n_batch, 2^n_open].
+        ``slices_in_flight`` slices run per kernel launch (default: all of
+        the range, within the limits of ``default_slices_in_flight``).
         """
         torch = self._torch
         if s1 is None:
             s1 = 1 << self.n_sliced
+        if slices_in_flight is None:
+            slices_in_flight = self.default_slices_in_flight(max(1, s1 - s0))
         if proj is None:
             proj = [0]
         proj_arr = np.ascontiguousarray(np.asarray(list(proj), dtype=np.uint64))
@@ -166,7 +179,7 @@ class Plan:
         if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous()
                 and out.numel() == nb << self.n_open):
             raise ValueError("out must be a contiguous complex128 CUDA tensor [n_batch, 2^n_open]")
-        ws = self.workspace()
+        ws = self.workspace(slices_in_flight)
         flags = (C.STEM_ACCUMULATE if accumulate else 0) | (C.STEM_TIME_STEPS if time_steps else 0)
         C.check(C.lib().stem_contract(
             self._h, int(s0), int(s1), _ptr(proj_arr, ctypes.c_uint64), nb,

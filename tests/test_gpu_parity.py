@@ -97,6 +97,11 @@ def test_sliced_sum_and_accumulate(cfg):
     # empty range writes zeros
     z = plan.contract(1, 1, proj=projs)
     assert torch.count_nonzero(z).item() == 0
+    # any number of slices per launch gives the same bits: every slice is
+    # computed the same way and added in slice order
+    for group in (1, 3, 1 << n_sl):
+        g = plan.contract(0, 1 << n_sl, proj=projs, slices_in_flight=group)
+        assert torch.equal(g, full), group
     plan.close()
 
 
@@ -117,6 +122,10 @@ def test_range_and_workspace_errors():
                                ctypes.c_void_p(out.data_ptr()), 0,
                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert st == C.STEM_ENOMEM
+    with pytest.raises(C.StemError) as e:
+        plan.workspace_bytes(0)
+    assert e.value.status == C.STEM_ERANGE
+    assert plan.workspace_bytes(8) == 8 * plan.workspace_bytes(1)
     plan.close()
 
 
