@@ -178,6 +178,32 @@ stem_status stem_contract(stem_plan_t plan, uint64_t s0, uint64_t s1,
                           uint32_t flags, void* stream);
 
 /*
+ * Many slice ranges, of one or several plans (different circuits), as one
+ * HIP graph launched with one call (paper §A.1: slices are independent
+ * subtasks; running many at once fills the GPU when each stem is small).
+ * stem_batch_create records, for plan j, the stem_contract work of slices
+ * [s0[j], s1[j]) with projected assignment proj[j] (NULL: all 0) into
+ * out[j] (device complex128 [2^n_open of plan j]) on a stream of its own,
+ * all forked from and joined back to `stream`, and instantiates the graph.
+ * The workspace (device, ws_bytes) is split into n equal 256-byte-aligned
+ * parts, one per plan; each must hold at least one slice of its plan
+ * (else STEM_ENOMEM).  flags: STEM_ACCUMULATE as for stem_contract;
+ * STEM_TIME_STEPS is not allowed (STEM_EINVAL).  Nothing runs until
+ * stem_batch_launch, which may be called any number of times; each launch
+ * recomputes out[j] from the plans' current device data (or adds to it
+ * with STEM_ACCUMULATE).  Plans, workspace and outputs must outlive the
+ * batch; a plan must not be used by two launches that overlap in time.
+ */
+typedef struct stem_batch_s* stem_batch_t;
+
+stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_t* s0,
+                              const uint64_t* s1, const uint64_t* proj, double* const* out,
+                              void* ws, uint64_t ws_bytes, uint32_t flags, void* stream,
+                              stem_batch_t* batch);
+stem_status stem_batch_launch(stem_batch_t batch, void* stream);
+stem_status stem_batch_destroy(stem_batch_t batch);
+
+/*
  * Fill dst (device, n complex64) with the counter-based test tensor: entry i
  * takes SplitMix64 outputs 4i..4i+3 of stream `seed` (Steele, Lea and Flood,
  * OOPSLA 2014); each 64-bit output gives two 22-bit integers (bits 42-63 and

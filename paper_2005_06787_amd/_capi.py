@@ -86,6 +86,15 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32,
                                        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                        ctypes.c_uint32, ctypes.c_void_p]),
+    "stem_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                           ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "stem_batch_launch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "stem_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "stem_fill_counter": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.c_int32, ctypes.c_void_p]),
     "stem_xeb_f64": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,

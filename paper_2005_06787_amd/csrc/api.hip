@@ -296,11 +296,13 @@ stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* i
   return STEM_OK;
 }
 
-stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_t* proj_assign,
-                          uint32_t n_batch, void* ws, uint64_t ws_bytes, double* out,
-                          uint32_t flags, void* stream) {
+}  // extern "C"
+
+// The slice loop of stem_contract; also recorded into graphs by stem_batch_create.
+static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
+                                 const uint64_t* proj_assign, uint32_t n_batch, void* ws,
+                                 uint64_t ws_bytes, double* out, uint32_t flags, hipStream_t st) {
   if (!p || !out) return fail(STEM_EINVAL, "null plan or output");
-  hipStream_t st = (hipStream_t)stream;
   const PlanLayout& L = p->L;
   const int n_sl = (int)L.sliced.size(), n_pr = (int)L.proj.size();
   const uint64_t n_slices = 1ull << n_sl;
@@ -368,7 +370,7 @@ stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_
         bop.vstride = (int64_t)p->sd[i].bstride;
         bop.sel = bsel[i];
         if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 2], st));
-        hipError_t e = launch_cgemm(p->precision, cur, bop, o, c0, nz, S.M, S.K, S.N, S.gemm, st);
+        hipError_t e = launch_cgemm(p->precision, cur, bop, o, c0, nz, S.M, S.K, S.N, S.gemm, S.sched, st);
         if (e != hipSuccess) return fail(STEM_EHIP, std::string("product: ") + hipGetErrorString(e));
         if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 3], st));
         cur = o;
@@ -379,6 +381,116 @@ stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_
     }
   }
   if (timing) p->timed_pending = true;
+  return STEM_OK;
+}
+
+struct stem_batch_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> events;  // fork, then one join per plan
+  int device = 0;
+};
+
+static void free_batch(stem_batch_s* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  delete b;
+}
+
+// Record every plan's range on its own stream, forked from and joined to st.
+static stem_status batch_record(stem_batch_s* b, int32_t n, const stem_plan_t* plans,
+                                const uint64_t* s0, const uint64_t* s1, const uint64_t* proj,
+                                double* const* out, unsigned char* ws, uint64_t part,
+                                uint32_t flags, hipStream_t st) {
+  HIPCHK(hipEventRecord(b->events[0], st));
+  for (int32_t j = 0; j < n; ++j) {
+    HIPCHK(hipStreamWaitEvent(b->side[j], b->events[0], 0));
+    const uint64_t pa = proj ? proj[j] : 0;
+    stem_status s = contract_impl(plans[j], s0[j], s1[j], &pa, 1, ws + part * j, part, out[j],
+                                  flags, b->side[j]);
+    if (s != STEM_OK) return s;
+    HIPCHK(hipEventRecord(b->events[1 + j], b->side[j]));
+    HIPCHK(hipStreamWaitEvent(st, b->events[1 + j], 0));
+  }
+  return STEM_OK;
+}
+
+extern "C" {
+
+stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_t* proj_assign,
+                          uint32_t n_batch, void* ws, uint64_t ws_bytes, double* out,
+                          uint32_t flags, void* stream) {
+  return contract_impl(p, s0, s1, proj_assign, n_batch, ws, ws_bytes, out, flags,
+                       (hipStream_t)stream);
+}
+
+stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_t* s0,
+                              const uint64_t* s1, const uint64_t* proj, double* const* out,
+                              void* ws, uint64_t ws_bytes, uint32_t flags, void* stream,
+                              stem_batch_t* batch) {
+  if (!batch) return fail(STEM_EINVAL, "null batch output");
+  *batch = nullptr;
+  if (n < 1 || !plans || !s0 || !s1 || !out) return fail(STEM_EINVAL, "empty or null batch");
+  if (flags & STEM_TIME_STEPS) return fail(STEM_EINVAL, "STEM_TIME_STEPS is not allowed in a batch");
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t part = (ws_bytes / (uint64_t)n) & ~255ull;
+  for (int32_t j = 0; j < n; ++j) {
+    if (!plans[j] || !out[j]) return fail(STEM_EINVAL, "null plan or output in batch");
+    if (s0[j] > s1[j] || s1[j] > (1ull << plans[j]->L.sliced.size()))
+      return fail(STEM_ERANGE, "slice range of plan " + std::to_string(j) + " out of range");
+    const uint64_t per = slice_ws_bytes(plans[j]);
+    if (per && (!ws || part < per))
+      return fail(STEM_ENOMEM, "workspace part of " + std::to_string(part) + " bytes for plan " +
+                                   std::to_string(j) + ", need " + std::to_string(per));
+  }
+  stem_batch_s* b = nullptr;
+  try {
+    b = new stem_batch_s();
+  } catch (const std::bad_alloc&) {
+    return fail(STEM_ENOMEM, "host allocation failed");
+  }
+  auto bail = [&](stem_status s) {
+    free_batch(b);
+    return s;
+  };
+  if (hipGetDevice(&b->device) != hipSuccess) return bail(fail(STEM_EHIP, "hipGetDevice failed"));
+  b->side.resize(n, nullptr);
+  b->events.resize(n + 1, nullptr);
+  for (auto& s : b->side)
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(STEM_EHIP, "hipStreamCreateWithFlags failed"));
+  for (auto& e : b->events)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(STEM_EHIP, "hipEventCreate failed"));
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bail(fail(STEM_EHIP, std::string("begin capture: ") + hipGetErrorString(e)));
+  stem_status rs = batch_record(b, n, plans, s0, s1, proj, out, (unsigned char*)ws, part, flags, st);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(st, &g);
+  b->graph = g;
+  if (rs != STEM_OK) return bail(rs);
+  if (e != hipSuccess) return bail(fail(STEM_EHIP, std::string("end capture: ") + hipGetErrorString(e)));
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(fail(STEM_EHIP, std::string("instantiate: ") + hipGetErrorString(e)));
+  *batch = b;
+  return STEM_OK;
+}
+
+stem_status stem_batch_launch(stem_batch_t batch, void* stream) {
+  if (!batch) return fail(STEM_EINVAL, "null batch");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != batch->device) return fail(STEM_EINVAL, "batch was created on another device");
+  HIPCHK(hipGraphLaunch(batch->exec, (hipStream_t)stream));
+  return STEM_OK;
+}
+
+stem_status stem_batch_destroy(stem_batch_t batch) {
+  free_batch(batch);
   return STEM_OK;
 }
 

@@ -44,7 +44,7 @@ hipError_t launch_permute(const Operand& in, const Operand& out, const PermArgs&
                           int nz, hipStream_t st);
 hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const Operand& C,
                         uint64_t s0, int nz, int64_t M, int64_t K, int64_t N,
-                        const GemmLayout& lay, hipStream_t st);
+                        const GemmLayout& lay, const GemmSched& sched, hipStream_t st);
 // out[o] += sum over z < nz (in order) of in_z[i], o = i re-ordered by m.
 hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, const BitMap& m,
                           hipStream_t st);

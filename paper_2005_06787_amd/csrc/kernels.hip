@@ -93,31 +93,35 @@ hipError_t launch_permute(const Operand& in, const Operand& out, const PermArgs&
 // ---------------------------------------------------------------------------
 // Complex product C[M x N] = A[M x K] . B[K x N] of one stem step.
 //
-// Operand addressing.  A is the stem: its entry (m, k) sits at complex index
-//   K-fast (AM = 0): m K + k            -- the summed labels are the s fastest
-//   M-fast (AM = 1): ins(m) | kpos(k)   -- the 4 fastest address bits belong
-//                                          to M, the s summed labels sit at
-//                                          arbitrary positions spos[]
-// where ins(m) spreads m's bits over the non-summed positions and kpos(k)
-// places k's bits at spos[].  Both avoid a separate permute pass: in K-fast
-// mode each row is a contiguous K-vector, in M-fast mode the 16 rows of a
-// block are 16 consecutive entries (128 B) for every k.
+// Operand addressing (GemmLayout).  A is the stem: row m starts at
+// lo(m & 15) | spread(m >> 4) and entry k sits kpos(k) further, so any
+// order of the stem's labels is read in place:
+//   K-low (AM = 0): k bits 0..2 are the 3 fastest address bits; lane group
+//                   g reads k = 2g, 2g+1 of its row as one 16-byte vector
+//                   and the 4 groups cover 64 contiguous bytes of the row;
+//   M-fast (AM = 1): the 4 low bits of m are the 4 fastest address bits, so
+//                   the 16 rows of a block are 128 contiguous bytes per k.
 // C is the next stem: entry (m, n) goes to
-//   N-fast (CM = 0): m N + n                      (new labels fastest)
-//   M-fast (CM = 1): (m>>4) 2^(4+f) | n 2^4 | (m&15)  (the 4 fastest M labels
-//                                          stay fastest, new labels above them)
+//   N-fast (CM = 0): m N + n                           (when M < 16)
+//   CM = 1:          (m>>4) 2^(4+f) | n 2^4 | (m&15)   (the 4 labels of m's
+//                   low bits become the output's fastest, new labels above)
+// so the next step can read the output M-fast, and the host chooses which
+// 4 labels sit at the bottom without a separate permute pass.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int64_t spread_rows(int64_t m, const GemmGeom& g) {
-  int64_t a = m;
+__device__ __forceinline__ int64_t row_base(int64_t m, const GemmGeom& g) {
+  int64_t lo = 0;
 #pragma unroll
-  for (int i = 0; i < kMaxShared; ++i) {
-    if (i < g.s) {
-      const int p = g.sins[i];
+  for (int b = 0; b < 4; ++b) lo |= ((m >> b) & 1ll) << g.mlo[b];
+  int64_t a = m >> 4;
+#pragma unroll
+  for (int i = 0; i < kMaxShared + 4; ++i) {
+    if (i < g.nins) {
+      const int p = g.ins[i];
       a = ((a >> p) << (p + 1)) | (a & ((1ll << p) - 1));
     }
   }
-  return a;
+  return a | lo;
 }
 
 __device__ __forceinline__ int64_t k_offset(int k, const GemmGeom& g) {
@@ -128,13 +132,8 @@ __device__ __forceinline__ int64_t k_offset(int k, const GemmGeom& g) {
   return a;
 }
 
-template <int AM>
-__device__ __forceinline__ int64_t row_base(int64_t m, const GemmGeom& g) {
-  return AM == 0 ? m * (int64_t)g.K : spread_rows(m, g);
-}
-
 // 4 consecutive reals A[m][kr0 .. kr0+3] (= complex k0 = kr0/2 and k0+1);
-// ko0/ko1 are the M-fast offsets of those two k values.
+// ko0/ko1 are the offsets of those two k values (adjacent in K-low mode).
 template <int AM>
 __device__ __forceinline__ f32x4 load_kr4(const float* __restrict__ A, int64_t rb, int kr0,
                                           int64_t ko0, int64_t ko1, const GemmGeom& g) {
@@ -142,7 +141,7 @@ __device__ __forceinline__ f32x4 load_kr4(const float* __restrict__ A, int64_t r
   if (rb < 0) return v;
   if (AM == 0) {
     if (kr0 < g.Kr) {
-      const float* src = A + 2 * rb + kr0;
+      const float* src = A + 2 * (rb + ko0);
       if (g.Kr >= 4) {
         v = *(const f32x4*)src;
       } else {
@@ -237,14 +236,14 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
       const int64_t row = row0 + t * 16 + r16;
-      rb[t] = row < g.M ? row_base<AM>(row, g) : -1;
+      rb[t] = row < g.M ? row_base(row, g) : -1;
 #pragma unroll
       for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     f32x4 a[TM];
     {
       const int kr0 = grp * 4;
-      const int64_t ko0 = AM == 1 ? k_offset(kr0 >> 1, g) : 0;
+      const int64_t ko0 = k_offset(kr0 >> 1, g);
       const int64_t ko1 = AM == 1 ? k_offset((kr0 >> 1) + 1, g) : 0;
 #pragma unroll
       for (int t = 0; t < TM; ++t) a[t] = load_kr4<AM>(A, rb[t], kr0, ko0, ko1, g);
@@ -254,7 +253,7 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
       f32x4 an[TM];
       if (kc + 1 < g.KC) {
         const int kr1 = (kc + 1) * 16 + grp * 4;
-        const int64_t ko0 = AM == 1 ? k_offset(kr1 >> 1, g) : 0;
+        const int64_t ko0 = k_offset(kr1 >> 1, g);
         const int64_t ko1 = AM == 1 ? k_offset((kr1 >> 1) + 1, g) : 0;
 #pragma unroll
         for (int t = 0; t < TM; ++t) an[t] = load_kr4<AM>(A, rb[t], kr1, ko0, ko1, g);
@@ -343,48 +342,77 @@ static GemmGeom make_geom(const GemmLayout& lay, int64_t M, int64_t K, int64_t N
   g.NT = std::max(16, g.Nr) / 16;
   g.s = lay.s;
   g.f = lay.f;
-  for (int i = 0; i < 16; ++i) {
-    g.spos[i] = lay.spos[i];
-    g.sins[i] = lay.sins[i];
-  }
+  for (int i = 0; i < 16; ++i) g.spos[i] = lay.spos[i];
+  for (int i = 0; i < 4; ++i) g.mlo[i] = lay.mlo[i];
+  g.nins = lay.nins;
+  for (int i = 0; i < 20; ++i) g.ins[i] = lay.ins[i];
   return g;
+}
+
+// Schedule with the defaults filled in (see GemmSched).
+static GemmSched resolve_sched(const GemmGeom& g, GemmSched s) {
+  int nt2 = 1;
+  while (nt2 < g.NT) nt2 <<= 1;
+  if (s.ntw <= 0) s.ntw = std::min(8, nt2);
+  s.ntw = std::min(s.ntw, std::min(8, nt2));
+  if (s.tm <= 0) s.tm = s.ntw <= 2 ? 4 : 2;
+  if (s.blocks <= 0) s.blocks = kTargetBlocks;
+  return s;
 }
 
 // Grid of a product launch: x row-block groups (each workgroup loops over
 // row blocks when there are more than the target), y column chunks, z slices.
-static dim3 gemm_grid(const GemmGeom& g, int TM, int NTW, int nz) {
+static dim3 gemm_grid(const GemmGeom& g, int TM, int NTW, int nz, int target) {
   const int64_t rows_per_wg = 4 * 16 * TM;
   const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
   const int gy = (g.NT + NTW - 1) / NTW;
-  const int64_t want = std::max<int64_t>(1, kTargetBlocks / ((int64_t)gy * nz));
+  const int64_t want = std::max<int64_t>(1, target / ((int64_t)gy * nz));
   const int64_t gx = std::min<int64_t>(nblk, want);
   return dim3((unsigned)gx, (unsigned)gy, (unsigned)nz);
 }
 
+struct LaunchCtx {
+  const Operand* A;
+  const Operand* B;
+  const Operand* C;
+  uint64_t s0;
+  int nz;
+  GemmGeom g;
+  GemmSched sch;
+  hipStream_t st;
+};
+
 template <int TM, int NTW, int AM, int CM>
-static void launch_f32_t(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
-                         int nz, const GemmGeom& g, hipStream_t st) {
-  const dim3 grid = gemm_grid(g, TM, NTW, nz);
-  const size_t lds = (size_t)g.KC * NTW * 256 * 4;
-  if (lds <= (size_t)kLdsBudget)
-    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1>), grid, dim3(256), lds, st, A,
-                       B, C, s0, g);
+static void launch_f32_t(const LaunchCtx& c) {
+  const dim3 grid = gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks);
+  const size_t lds = (size_t)c.g.KC * NTW * 256 * 4;
+  if (lds <= (size_t)kLdsBudget && c.sch.lds != 0)
+    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1>), grid, dim3(256), lds, c.st,
+                       *c.A, *c.B, *c.C, c.s0, c.g);
   else
-    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 0>), grid, dim3(256), 0, st, A, B,
-                       C, s0, g);
+    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 0>), grid, dim3(256), 0, c.st,
+                       *c.A, *c.B, *c.C, c.s0, c.g);
 }
 
+#define STEM_TM_NTW_DISPATCH(FN, ...)                                        \
+  switch (c.sch.tm * 16 + c.sch.ntw) {                                       \
+    case 16 + 1: FN<1, 1, __VA_ARGS__>(c); break;                            \
+    case 16 + 2: FN<1, 2, __VA_ARGS__>(c); break;                            \
+    case 16 + 4: FN<1, 4, __VA_ARGS__>(c); break;                            \
+    case 16 + 8: FN<1, 8, __VA_ARGS__>(c); break;                            \
+    case 32 + 1: FN<2, 1, __VA_ARGS__>(c); break;                            \
+    case 32 + 2: FN<2, 2, __VA_ARGS__>(c); break;                            \
+    case 32 + 4: FN<2, 4, __VA_ARGS__>(c); break;                            \
+    case 32 + 8: FN<2, 8, __VA_ARGS__>(c); break;                            \
+    case 64 + 1: FN<4, 1, __VA_ARGS__>(c); break;                            \
+    case 64 + 2: FN<4, 2, __VA_ARGS__>(c); break;                            \
+    case 64 + 4: FN<4, 4, __VA_ARGS__>(c); break;                            \
+    default: FN<4, 8, __VA_ARGS__>(c); break;                                \
+  }
+
 template <int AM, int CM>
-static void launch_f32_m(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
-                         int nz, const GemmGeom& g, hipStream_t st) {
-  if (g.NT <= 1)
-    launch_f32_t<4, 1, AM, CM>(A, B, C, s0, nz, g, st);
-  else if (g.NT <= 2)
-    launch_f32_t<4, 2, AM, CM>(A, B, C, s0, nz, g, st);
-  else if (g.NT <= 4)
-    launch_f32_t<2, 4, AM, CM>(A, B, C, s0, nz, g, st);
-  else
-    launch_f32_t<2, 8, AM, CM>(A, B, C, s0, nz, g, st);
+static void launch_f32_m(const LaunchCtx& c) {
+  STEM_TM_NTW_DISPATCH(launch_f32_t, AM, CM)
 }
 
 // ---------------------------------------------------------------------------
@@ -476,17 +504,15 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
       const int64_t row = row0 + t * 16 + r16;
-      rb[t] = row < g.M ? row_base<AM>(row, g) : -1;
+      rb[t] = row < g.M ? row_base(row, g) : -1;
 #pragma unroll
       for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     for (int kc = 0; kc < g.KC; ++kc) {
       const int kr0 = kc * 32 + grp * 8;
-      int64_t ko[4] = {0, 0, 0, 0};
-      if (AM == 1) {
+      int64_t ko[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ko[i] = k_offset((kr0 >> 1) + i, g);
-      }
+      for (int i = 0; i < 4; ++i) ko[i] = k_offset((kr0 >> 1) + i, g);
       vec ahi[TM], alo[TM];
       float inv_a[TM];
 #pragma unroll
@@ -613,63 +639,62 @@ int build_bfrag_split(const float* b, int64_t K, int64_t N, int bf16, uint16_t* 
 }
 
 template <int TM, int NTW, int BF16, int AM, int CM>
-static void launch_split_t(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
-                           int nz, const GemmGeom& g, hipStream_t st) {
-  const dim3 grid = gemm_grid(g, TM, NTW, nz);
-  const size_t lds = (size_t)g.KC * NTW * 512 * 2 * 2;
-  if (lds <= (size_t)kLdsBudget)
+static void launch_split_t(const LaunchCtx& c) {
+  const dim3 grid = gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks);
+  const size_t lds = (size_t)c.g.KC * NTW * 512 * 2 * 2;
+  if (lds <= (size_t)kLdsBudget && c.sch.lds != 0)
     hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1>), grid, dim3(256), lds,
-                       st, A, B, C, s0, g);
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else
     hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 0>), grid, dim3(256), 0,
-                       st, A, B, C, s0, g);
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
 }
 
 template <int BF16, int AM, int CM>
-static void launch_split_n(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
-                           int nz, const GemmGeom& g, hipStream_t st) {
-  if (g.NT <= 1)
-    launch_split_t<4, 1, BF16, AM, CM>(A, B, C, s0, nz, g, st);
-  else if (g.NT <= 2)
-    launch_split_t<4, 2, BF16, AM, CM>(A, B, C, s0, nz, g, st);
-  else if (g.NT <= 4)
-    launch_split_t<2, 4, BF16, AM, CM>(A, B, C, s0, nz, g, st);
-  else
-    launch_split_t<2, 8, BF16, AM, CM>(A, B, C, s0, nz, g, st);
+static void launch_split_n(const LaunchCtx& c) {
+  STEM_TM_NTW_DISPATCH(launch_split_t, BF16, AM, CM)
 }
 
 template <int BF16>
-static void launch_split_b(const Operand& A, const Operand& B, const Operand& C, uint64_t s0,
-                           int nz, const GemmGeom& g, const GemmLayout& lay, hipStream_t st) {
+static void launch_split_b(const LaunchCtx& c, const GemmLayout& lay) {
   if (lay.amode == 0 && lay.cmode == 0)
-    launch_split_n<BF16, 0, 0>(A, B, C, s0, nz, g, st);
+    launch_split_n<BF16, 0, 0>(c);
   else if (lay.amode == 0)
-    launch_split_n<BF16, 0, 1>(A, B, C, s0, nz, g, st);
+    launch_split_n<BF16, 0, 1>(c);
   else if (lay.cmode == 0)
-    launch_split_n<BF16, 1, 0>(A, B, C, s0, nz, g, st);
+    launch_split_n<BF16, 1, 0>(c);
   else
-    launch_split_n<BF16, 1, 1>(A, B, C, s0, nz, g, st);
+    launch_split_n<BF16, 1, 1>(c);
 }
 
 hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const Operand& C,
                         uint64_t s0, int nz, int64_t M, int64_t K, int64_t N,
-                        const GemmLayout& lay, hipStream_t st) {
+                        const GemmLayout& lay, const GemmSched& sched, hipStream_t st) {
+  LaunchCtx c;
+  c.A = &A;
+  c.B = &B;
+  c.C = &C;
+  c.s0 = s0;
+  c.nz = nz;
+  c.st = st;
   if (precision == STEM_FP32) {
-    const GemmGeom g = make_geom(lay, M, K, N, 16);
+    c.g = make_geom(lay, M, K, N, 16);
+    c.sch = resolve_sched(c.g, sched);
     if (lay.amode == 0 && lay.cmode == 0)
-      launch_f32_m<0, 0>(A, B, C, s0, nz, g, st);
+      launch_f32_m<0, 0>(c);
     else if (lay.amode == 0)
-      launch_f32_m<0, 1>(A, B, C, s0, nz, g, st);
+      launch_f32_m<0, 1>(c);
     else if (lay.cmode == 0)
-      launch_f32_m<1, 0>(A, B, C, s0, nz, g, st);
+      launch_f32_m<1, 0>(c);
     else
-      launch_f32_m<1, 1>(A, B, C, s0, nz, g, st);
+      launch_f32_m<1, 1>(c);
   } else {
-    const GemmGeom g = make_geom(lay, M, K, N, 32);
+    c.g = make_geom(lay, M, K, N, 32);
+    c.sch = resolve_sched(c.g, sched);
     if (precision == STEM_SPLIT_BF16)
-      launch_split_b<1>(A, B, C, s0, nz, g, lay, st);
+      launch_split_b<1>(c, lay);
     else
-      launch_split_b<0>(A, B, C, s0, nz, g, lay, st);
+      launch_split_b<0>(c, lay);
   }
   return hipGetLastError();
 }

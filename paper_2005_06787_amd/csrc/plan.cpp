@@ -310,74 +310,116 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
              std::to_string(st.f) + " (at most 16 each)";
       return STEM_ESHAPE;
     }
-    // Operand addressing (no permute pass) when either the 4 fastest stem
-    // labels are all kept (M-fast) or the summed labels are exactly the s
-    // fastest ones (K-fast).  Otherwise one permute re-stores the stem with
-    // the 4 kept labels that are needed latest as its fastest bits.
+    // Operand addressing: the product reads the stem in place when its 4
+    // fastest labels are all kept (M-fast) or its min(s, 3) fastest labels
+    // are all summed (K-low); otherwise one permute re-stores it.  The 4
+    // labels that become the output's fastest are the input's 4 fastest in
+    // M-fast mode and otherwise the 4 kept labels whose next use is latest.
     std::set<int32_t> shared_set(shared.begin(), shared.end());
     const int m_bits = R - s;
-    bool bottom_kept = R >= 4;
-    for (int j = std::max(0, R - 4); j < R && bottom_kept; ++j)
-      if (shared_set.count(cur[j])) bottom_kept = false;
-    std::set<int32_t> tail(cur.end() - s, cur.end());
+    const int n_lo = std::min(4, m_bits);
+    // Labels for the output's `count` fastest bits (bit 0 first).  Best: 3 or
+    // more kept labels that a later step sums together (the latest such
+    // step), so that step finds its 3 fastest bits summed and runs K-low,
+    // with a 4th label needed no earlier; else the labels needed latest.
+    auto latest = [&](const std::vector<int32_t>& kept, int count) {
+      std::vector<std::pair<int, int>> by_use;  // (next use, position in kept)
+      for (int j = 0; j < (int)kept.size(); ++j) by_use.push_back({next_use(kept[j], i), j});
+      std::stable_sort(by_use.begin(), by_use.end(),
+                       [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+                         return a.first > b.first;
+                       });
+      std::vector<int32_t> out;
+      if (count == 4) {
+        for (size_t a = 0; a < by_use.size(); ) {
+          size_t b = a;
+          while (b < by_use.size() && by_use[b].first == by_use[a].first) ++b;
+          if (b - a >= 3) {
+            for (size_t j = a; j < b && out.size() < 4; ++j) out.push_back(kept[by_use[j].second]);
+            // a 4th label needed no earlier than the group: the latest one left
+            for (size_t j = 0; j < a && out.size() < 4; ++j) out.push_back(kept[by_use[j].second]);
+            if (out.size() == 4) return out;
+            out.clear();
+          }
+          a = b;
+        }
+      }
+      // the labels needed latest; the earliest-needed one at bit 0
+      for (int j = count - 1; j >= 0; --j) out.push_back(kept[by_use[j].second]);
+      return out;
+    };
+    bool bottom_kept = m_bits >= 4;
+    for (int q = 0; q < 4 && bottom_kept; ++q)
+      if (shared_set.count(cur[R - 1 - q])) bottom_kept = false;
+    bool low_summed = true;
+    for (int q = 0; q < std::min(s, 3); ++q)
+      if (!shared_set.count(cur[R - 1 - q])) low_summed = false;
     GemmLayout& G = st.gemm;
     std::memset(&G, 0, sizeof(G));
-    if (m_bits >= 4 && bottom_kept) {
+    std::vector<int32_t> mlo_labels;  // m bit 0 first
+    if (bottom_kept) {
       st.permuted = false;
       st.labels_gemm = cur;
       G.amode = 1;
-    } else if (tail == shared_set) {
+      for (int q = 0; q < 4; ++q) mlo_labels.push_back(cur[R - 1 - q]);
+    } else if (low_summed) {
       st.permuted = false;
       st.labels_gemm = cur;
       G.amode = 0;
+      mlo_labels = latest(keep, n_lo);
     } else {
       st.permuted = true;
       if (m_bits >= 4) {
-        // the 4 kept labels whose next use is latest become the fastest bits
-        std::vector<std::pair<int, int>> by_use;  // (next use, position in keep)
-        for (int j = 0; j < (int)keep.size(); ++j) by_use.push_back({next_use(keep[j], i), j});
-        std::stable_sort(by_use.begin(), by_use.end(),
-                         [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
-                           return a.first > b.first;
-                         });
-        std::set<int> low;
-        for (int j = 0; j < 4; ++j) low.insert(by_use[j].second);
-        std::vector<int32_t> top, bottom;
-        for (int j = 0; j < (int)keep.size(); ++j) (low.count(j) ? bottom : top).push_back(keep[j]);
-        st.labels_gemm = top;
+        const std::vector<int32_t> b4 = latest(keep, 4);
+        const std::set<int32_t> b4s(b4.begin(), b4.end());
+        for (int32_t x : keep)
+          if (!b4s.count(x)) st.labels_gemm.push_back(x);
         st.labels_gemm.insert(st.labels_gemm.end(), shared.begin(), shared.end());
-        st.labels_gemm.insert(st.labels_gemm.end(), bottom.begin(), bottom.end());
+        for (int q = 3; q >= 0; --q) st.labels_gemm.push_back(b4[q]);
+        mlo_labels = b4;
         G.amode = 1;
       } else {
         st.labels_gemm = keep;
         st.labels_gemm.insert(st.labels_gemm.end(), shared.begin(), shared.end());
+        mlo_labels = latest(keep, n_lo);
         G.amode = 0;
       }
       st.perm = make_perm(cur, st.labels_gemm);
       L->max_ws_rank = std::max(L->max_ws_rank, R);
     }
-    // summed labels in the order they have in the stem read by the product
+    auto pos_of = [&](int32_t x) {
+      return R - 1 - (int)(std::find(st.labels_gemm.begin(), st.labels_gemm.end(), x) -
+                           st.labels_gemm.begin());
+    };
+    // k index: summed labels in the order of the stem read by the product,
+    // so k's low bits are its fastest summed labels
     std::vector<int32_t> kept_g;
     st.sigma.clear();
     for (int32_t x : st.labels_gemm) (shared_set.count(x) ? st.sigma : kept_g).push_back(x);
     G.s = s;
     G.f = st.f;
-    for (int j = 0; j < s; ++j) {
-      const int pos_in_list = (int)(std::find(st.labels_gemm.begin(), st.labels_gemm.end(),
-                                              st.sigma[j]) - st.labels_gemm.begin());
-      G.spos[s - 1 - j] = R - 1 - pos_in_list;
+    for (int j = 0; j < s; ++j) G.spos[s - 1 - j] = pos_of(st.sigma[j]);
+    // m index: bits 0..3 at the chosen labels, the rest in address order
+    std::vector<int32_t> ins;
+    for (int j = 0; j < s; ++j) ins.push_back(G.spos[j]);
+    const std::set<int32_t> mlo_set(mlo_labels.begin(), mlo_labels.end());
+    for (int b = 0; b < (int)mlo_labels.size(); ++b) {
+      G.mlo[b] = pos_of(mlo_labels[b]);
+      ins.push_back(G.mlo[b]);
     }
-    for (int j = 0; j < s; ++j) G.sins[j] = G.spos[j];
-    std::sort(G.sins, G.sins + s);
+    std::sort(ins.begin(), ins.end());
+    G.nins = (int)ins.size();
+    for (int j = 0; j < G.nins; ++j) G.ins[j] = ins[j];
+    std::vector<int32_t> m_hi;  // most significant first
+    for (int32_t x : kept_g)
+      if (!mlo_set.count(x)) m_hi.push_back(x);
     G.cmode = m_bits >= 4 ? 1 : 0;
-    if (G.cmode == 1) {
-      st.labels_after.assign(kept_g.begin(), kept_g.end() - 4);
+    st.labels_after = m_hi;
+    if (G.cmode == 1)
       st.labels_after.insert(st.labels_after.end(), st.free_labels.begin(), st.free_labels.end());
-      st.labels_after.insert(st.labels_after.end(), kept_g.end() - 4, kept_g.end());
-    } else {
-      st.labels_after = kept_g;
+    for (int b = (int)mlo_labels.size() - 1; b >= 0; --b) st.labels_after.push_back(mlo_labels[b]);
+    if (G.cmode == 0)
       st.labels_after.insert(st.labels_after.end(), st.free_labels.begin(), st.free_labels.end());
-    }
     st.rank_out = (int)st.labels_after.size();
     if (st.rank_out > L->max_rank) {
       *err = "stem rank " + std::to_string(st.rank_out) + " after step " + std::to_string(i) +

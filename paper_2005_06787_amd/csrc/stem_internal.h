@@ -39,22 +39,44 @@ struct BitMap {
   int32_t dst[63];
 };
 
-// Operand addressing of one product (see the kernels): amode 0 = K-fast
-// (summed labels are the s fastest stem bits), 1 = M-fast (the 4 fastest
-// stem bits are not summed; summed labels anywhere); cmode 0 = N-fast (new
-// labels fastest in the output), 1 = M-fast (output keeps the 4 fastest row
-// labels fastest, new labels just above them).
+// Operand addressing of one product (see the kernels).  Row m of the stem
+// starts at lo(m & 15) | spread(m >> 4): the 4 low bits of m go to the
+// address positions mlo[], the others fill the positions not taken by the
+// summed labels or mlo[], in ascending order.  Entry k of a row is at
+// kpos(k): k bit i at position spos[i].
+//   amode 0 = K-low: k bits 0..2 are address bits 0..2 (or K < 8 and the
+//             summed labels are exactly the fastest ones), so a lane reads
+//             2 adjacent complex entries as one 16-byte vector;
+//   amode 1 = M-fast: mlo[] = 0..3, so the 16 rows of a block are 16
+//             consecutive entries for every k.
+//   cmode 0 = N-fast output: address m N + n (used when M < 16);
+//   cmode 1 = output order (rows by m >> 4), new labels, (rows by m & 15):
+//             address (m >> 4) 2^(4+f) | n 2^4 | (m & 15).
 struct GemmLayout {
   int32_t amode, cmode, s, f;
   int32_t spos[16];     // stem address position of k bit i (i = 0 least significant)
-  int32_t sins[16];     // the same positions, ascending
+  int32_t mlo[4];       // address positions of m bits 0..3
+  int32_t nins;         // positions to skip when spreading m >> 4 (summed + mlo)
+  int32_t ins[20];      // ascending
+};
+
+// Launch schedule of one product (chosen by the autotuner; 0 = default):
+// tm 16-row blocks per wave, at most ntw 16-column tiles per workgroup,
+// about `blocks` workgroups per launch, branch fragments in LDS or not.
+struct GemmSched {
+  int32_t tm = 0;       // 1, 2 or 4
+  int32_t ntw = 0;      // 1, 2, 4 or 8
+  int32_t blocks = 0;   // 256 .. 65536
+  int32_t lds = -1;     // 1 LDS, 0 global, -1 when it fits
 };
 
 struct GemmGeom {
   int64_t M;
   int32_t K, N, Kr, Nr, KC, NT, s, f;
   int32_t spos[16];
-  int32_t sins[16];
+  int32_t mlo[4];
+  int32_t nins;
+  int32_t ins[20];
 };
 
 constexpr int kMaxShared = 16;  // K <= 2^16
@@ -103,6 +125,7 @@ struct StepLayout {
   int32_t branch_index = 0;
   int64_t M = 0, K = 0, N = 0;
   GemmLayout gemm{};
+  GemmSched sched{};                   // autotuned launch schedule (0 = default)
   PermArgs perm{};                     // valid when permuted
 };
 

@@ -199,6 +199,54 @@ class Plan:
             pass
 
 
+class Batch:
+    """Slice ranges of several plans recorded as one HIP graph (C-ABI
+    stem_batch_*).  ``launch()`` replays it: every plan's output is
+    recomputed (or added to, with ``accumulate``)."""
+
+    def __init__(self, plans, ranges, proj=None, outs=None, ws_bytes: int | None = None,
+                 accumulate: bool = False, stream=None):
+        import torch
+
+        n = len(plans)
+        if len(ranges) != n:
+            raise ValueError("one (s0, s1) range per plan")
+        self.plans = list(plans)
+        self.outs = outs if outs is not None else [
+            torch.empty(1 << p.n_open, dtype=torch.complex128, device="cuda") for p in plans]
+        if ws_bytes is None:
+            ws_bytes = 0
+            for p, (a, b) in zip(plans, ranges):
+                ws_bytes = max(ws_bytes, p.workspace_bytes(p.default_slices_in_flight(max(1, b - a))))
+            ws_bytes *= n
+        self.ws = torch.empty(max(256, int(ws_bytes)), dtype=torch.uint8, device="cuda")
+        hp = (ctypes.c_void_p * n)(*[p._h for p in plans])
+        a0 = (ctypes.c_uint64 * n)(*[int(r[0]) for r in ranges])
+        a1 = (ctypes.c_uint64 * n)(*[int(r[1]) for r in ranges])
+        pr = (ctypes.c_uint64 * n)(*([int(x) for x in proj] if proj is not None else [0] * n))
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
+        h = ctypes.c_void_p()
+        C.check(C.lib().stem_batch_create(
+            n, hp, a0, a1, pr, op, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+            C.STEM_ACCUMULATE if accumulate else 0, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        C.check(C.lib().stem_batch_launch(self._h, _stream_handle(stream)))
+        return self.outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            C.lib().stem_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def stem_fill_counter(dst, seed: int, scale_log2: int, stream=None) -> None:
     """Fill a complex64 CUDA tensor with the counter-based test tensor."""
     C.check(C.lib().stem_fill_counter(ctypes.c_void_p(dst.data_ptr()), dst.numel(), int(seed),
