@@ -49,6 +49,99 @@ def make_net():
     return net, cfg
 
 
+def batched_workload(steps: int, tune_cache=None):
+    """8 seeded 40-qubit circuits (5x8 grid, 10-14 cycles, sliced to widths
+    20-24), the first 512 slices of each, as one graph launch."""
+    import torch
+
+    from paper_2005_06787_amd import Batch, Plan, planner
+    from workloads import tensors
+    from workloads.circuits import block_qubits, make_circuit
+
+    cycles = [10, 11, 12, 13, 14, 10, 12, 14]
+    widths = [20, 21, 22, 23, 24, 21, 22, 24]
+    plans, ranges, flops = [], [], 0.0
+    t0 = time.perf_counter()
+    for j, (cyc, w) in enumerate(zip(cycles, widths)):
+        circ = make_circuit(5, 8, cyc, 400 + j)
+        oq = block_qubits(5, 8, range(0, 2), range(5, 8))
+        pre = tensors.split_open_prefix(40, oq, 1400 + j)
+        closed = dict(zip(pre["closed"], pre["closed_bits"]))
+        net = planner.plan_circuit(circ, oq, closed, max_width=w, trials=8, seed=j)
+        plan = Plan(net)
+        n = min(512, 1 << plan.n_sliced)
+        group = min(n, max(1, (8 << 30) // plan.workspace_bytes(1)))
+        plan.tune(slices_in_flight=group, reps=2, cache_path=tune_cache)
+        plans.append(plan)
+        ranges.append((0, n))
+        flops += plan.summary()["flops_per_slice"] * n
+        log(f"batched circuit {j}: {cyc} cycles, width {net['stats']['peak_width']}, "
+            f"{len(net['sliced_labels'])} sliced labels, group {group}")
+    log(f"batched workload planned and tuned in {time.perf_counter() - t0:.1f} s")
+    ws = sum(0 for _ in plans)  # noqa: F841
+    ws_bytes = len(plans) * max(p.workspace_bytes(min(r[1], max(1, (8 << 30) // p.workspace_bytes(1))))
+                                for p, r in zip(plans, ranges))
+    batch = Batch(plans, ranges, ws_bytes=ws_bytes)
+    batch.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.launch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    n_sl = sum(r[1] - r[0] for r in ranges)
+    out = {"workload": "8 circuits, 5x8 grid (40 qubits), 10-14 cycles, widths 20-24, "
+                       "first 512 slices each, one graph launch, FP32",
+           "slices": n_sl, "ms_per_launch": round(dt * 1e3, 3),
+           "slices_per_s": round(n_sl / dt, 1), "tflops": round(flops / dt / 1e12, 3)}
+    batch.close()
+    for p in plans:
+        p.close()
+    return out
+
+
+def isolated_stem(steps: int, tune_cache=None):
+    """The isolated stem at its real shape: a 2^30 complex64 stem (8 GiB),
+    40 steps with random complex Gaussian branches, in the three precisions."""
+    import torch
+
+    from paper_2005_06787_amd import Plan, stem_fill_counter
+    from workloads import configs
+    from workloads import tensors as wt
+
+    c = configs.ISOLATED_STEM
+    iso = wt.random_isolated_stem(c["n_rank"], c["n_steps"], seed=c["seed"])
+    x = torch.empty(1 << c["n_rank"], dtype=torch.complex64, device="cuda")
+    stem_fill_counter(x, iso["stem_seed"], iso["stem_scale_log2"])
+    net = {"open_labels": iso["final_labels"], "sliced_labels": [], "proj_labels": [],
+           "stem": {"labels": iso["stem_labels"]}, "branches": iso["branches"]}
+    out = {"workload": "isolated stem, 2^30 complex64, 40 steps, branches of rank 6-14 "
+                       "sharing 4-8 labels"}
+    for precision in ("fp32", "split_fp16", "split_bf16"):
+        plan = Plan(net, precision=precision, stem_device=x)
+        summ = plan.summary()
+        plan.tune(slices_in_flight=1, reps=2, cache_path=tune_cache)
+        res = plan.contract()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.contract(out=res)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[precision] = {"ms_per_chain": round(dt * 1e3, 3),
+                          "tflops": round(summ["flops_per_slice"] / dt / 1e12, 2),
+                          "algorithmic_gbs": round(summ["bytes_per_slice"] / dt / 1e9, 1)}
+        log(f"isolated stem {precision}: {dt * 1e3:.1f} ms, "
+            f"{summ['flops_per_slice'] / dt / 1e12:.1f} TFLOP/s")
+        del res
+        plan.close()
+    out["flops_per_chain"] = summ["flops_per_slice"]
+    out["bytes_per_chain"] = summ["bytes_per_slice"]
+    del x
+    torch.cuda.empty_cache()
+    return out
+
+
 def timed_run(plan, steps, warmup, n_slices, stream):
     import torch
 
@@ -132,6 +225,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-split", action="store_true", help="skip the split-FP16 run")
+    ap.add_argument("--no-tune", action="store_true", help="default launch schedules")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the isolated-stem and batched-circuit workloads")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache / measurement log")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -155,6 +252,11 @@ def main():
         plan = Plan(net, precision=precision)
         summ = plan.summary()
         n_slices = summ["n_slices"]
+        if not args.no_tune:
+            t0 = time.perf_counter()
+            plan.tune(slices_in_flight=plan.default_slices_in_flight(n_slices), reps=3,
+                      cache_path=args.tune_cache)
+            log(f"{precision}: schedules tuned in {time.perf_counter() - t0:.1f} s")
         dt, out = timed_run(plan, args.steps, args.warmup, n_slices, stream)
         ms = dt / args.steps * 1e3
         flops = summ["flops_per_slice"] * n_slices
@@ -214,9 +316,13 @@ def main():
                 worst = max(worst, stats.rel_l2(got, refs[s]))
             errs[precision] = worst
         line["amp_rel_l2_vs_oracle"] = errs
-    print(json.dumps(line), flush=True)
     for p in plans.values():
         p.close()
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        line["isolated_stem_2e30"] = isolated_stem(3, args.tune_cache)
+        line["batched_8_circuits"] = batched_workload(3, args.tune_cache)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -110,6 +110,14 @@ typedef struct stem_step_info {
   float last_gemm_us;     /* product launch of the last STEM_TIME_STEPS call, or -1;
                              one launch covers last_slices slices */
   float last_perm_us;     /* idem for the permute, or -1 */
+  int32_t amode;          /* product read mode: 0 K-low, 1 M-fast */
+  int32_t cmode;          /* product write mode: 0 N-fast, 1 fastest row labels kept */
+  int32_t sched_tm;       /* launch schedule in use (0 = default): row blocks per wave */
+  int32_t sched_ntw;      /* column tiles per workgroup */
+  int32_t sched_blocks;   /* target workgroups per launch */
+  int32_t sched_lds;      /* branch in LDS: 1, 0, or -1 = when it fits */
+  float tuned_us;         /* stem_tune's time of that schedule per launch, or -1 */
+  int32_t tuned_slices;   /* slices per launch stem_tune measured with */
 } stem_step_info;
 
 /* Summary of a plan, computed on the host without a GPU. */
@@ -178,13 +186,34 @@ stem_status stem_contract(stem_plan_t plan, uint64_t s0, uint64_t s1,
                           uint32_t flags, void* stream);
 
 /*
+ * Autotuner of the product kernels' launch schedules (rows per wave, column
+ * tiles per workgroup, workgroups per launch, branch in LDS or not).  For
+ * every step it times each candidate schedule with hipEvents at
+ * `slices_in_flight` slices per launch (reps launches each, after one
+ * untimed launch) on the caller's workspace (ws_bytes >=
+ * stem_plan_workspace_bytes(plan, slices_in_flight)), keeps the fastest in
+ * the plan (used by later stem_contract calls) and appends one text line
+ * per measurement to `cache_path` (NULL: no file):
+ *   stem-tune-v1 <precision> <amode> <cmode> <log2 M> <log2 K> <log2 N>
+ *                <slices> <tm> <ntw> <blocks> <lds> <microseconds>
+ * A step whose key (precision .. slices) already has lines in the file
+ * takes the fastest recorded schedule without measuring, unless reps < 0
+ * (then |reps| launches are timed and the file only gains lines).  The
+ * workspace contents are overwritten.  Synchronises `stream`.
+ */
+stem_status stem_tune(stem_plan_t plan, uint32_t slices_in_flight, void* ws, uint64_t ws_bytes,
+                      int32_t reps, const char* cache_path, void* stream);
+
+/*
  * Many slice ranges, of one or several plans (different circuits), as one
  * HIP graph launched with one call (paper §A.1: slices are independent
  * subtasks; running many at once fills the GPU when each stem is small).
  * stem_batch_create records, for plan j, the stem_contract work of slices
  * [s0[j], s1[j]) with projected assignment proj[j] (NULL: all 0) into
  * out[j] (device complex128 [2^n_open of plan j]) on a stream of its own,
- * all forked from and joined back to `stream`, and instantiates the graph.
+ * all forked from and joined back to a private recording stream (nothing
+ * is enqueued on `stream`, which is unused here and may be the null
+ * stream), and instantiates the graph.
  * The workspace (device, ws_bytes) is split into n equal 256-byte-aligned
  * parts, one per plan; each must hold at least one slice of its plan
  * (else STEM_ENOMEM).  flags: STEM_ACCUMULATE as for stem_contract;
@@ -202,6 +231,71 @@ stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_
                               stem_batch_t* batch);
 stem_status stem_batch_launch(stem_batch_t batch, void* stream);
 stem_status stem_batch_destroy(stem_batch_t batch);
+
+/*
+ * Step shapes of a descriptor, on the host without a GPU (the same layout
+ * decisions stem_plan_create makes; timing and schedule fields are -1/0).
+ * Writes min(*n_steps, capacity) entries; *n_steps receives the count.
+ */
+stem_status stem_plan_steps(const stem_plan_desc* desc, stem_step_info* steps, int32_t capacity,
+                            int32_t* n_steps);
+
+/* ---- runtime models (ranking candidate slicing sets and stem orders) ----
+ *
+ * Analytic model (paper §A.1 cost with a roofline per step): a product
+ * launch over g slices takes max(g 8 (MK+MN+KN) / hbm, g 8 MKN / peak) +
+ * launch, a permute g 16 2^rank / hbm + launch; peak is the precision's
+ * matrix rate (split paths do 3 products on the FP16/BF16 rate).  The
+ * result is seconds for all 2^n_sliced slices in groups of g.
+ */
+typedef struct stem_hw {
+  double hbm_bytes_per_s;     /* e.g. 8e12 */
+  double fp32_flops_per_s;    /* dense FP32 matrix rate, e.g. 157.3e12 */
+  double fp16_flops_per_s;    /* dense FP16/BF16 matrix rate, e.g. 2.5e15 */
+  double launch_s;            /* per kernel launch, e.g. 4e-6 */
+} stem_hw;
+
+stem_status stem_cost_analytic(const stem_step_info* steps, int32_t n_steps, int32_t precision,
+                               uint32_t slices_in_flight, uint64_t n_slices, const stem_hw* hw,
+                               double* seconds);
+
+/* Number of features of one step and the features themselves (host):
+ * log2 M, log2 K, log2 N, log2 slices per launch, amode, cmode, FP32,
+ * split FP16, split BF16, log2 algorithmic bytes per launch, log2 flops per
+ * launch, log2 analytic seconds per launch (default stem_hw). */
+#define STEM_N_FEATURES 12
+stem_status stem_step_features(const stem_step_info* step, int32_t precision,
+                               uint32_t slices_in_flight, float* features);
+
+/*
+ * Learned runtime model: y = W3^T relu(W2^T relu(W1^T x' + b1) + b2) + b3
+ * on standardised features x' = (x - mean) * inv_std, predicting the
+ * standardised log time (y t_std + t_mean = ln microseconds).  FP32, all
+ * arithmetic in HIP kernels; training minimises the mean squared error with
+ * full-batch Adam (Kingma and Ba 2015).  Parameters are packed as W1
+ * [F x H] row-major, b1 [H], W2 [H x H], b2 [H], W3 [H], b3 [1]; their
+ * initial values are inputs (host), so a caller's seeded initialisation is
+ * reproduced exactly.  Buffers x (n x F), t (n) and y (n) are device FP32.
+ */
+typedef struct stem_mlp_s* stem_mlp_t;
+
+int64_t stem_mlp_n_params(int32_t n_features, int32_t hidden);
+stem_status stem_mlp_create(int32_t n_features, int32_t hidden, const float* init_params,
+                            stem_mlp_t* mlp);
+stem_status stem_mlp_set_scaling(stem_mlp_t mlp, const float* x_mean, const float* x_inv_std,
+                                 float t_mean, float t_std);
+stem_status stem_mlp_get_params(stem_mlp_t mlp, float* params_host);
+/* Loss (device float[1]) and its gradient (device, packed like the
+ * parameters) on standardised targets t' = (t - t_mean) / t_std. */
+stem_status stem_mlp_loss_grad(stem_mlp_t mlp, const float* x, const float* t, int32_t n,
+                               float* loss, float* grad, void* stream);
+/* `steps` Adam updates (lr, beta1 0.9, beta2 0.999, eps 1e-8); loss after
+ * the last one into loss (device float[1], may be NULL). */
+stem_status stem_mlp_train(stem_mlp_t mlp, const float* x, const float* t, int32_t n,
+                           int32_t steps, float lr, float* loss, void* stream);
+/* y = predicted ln microseconds. */
+stem_status stem_mlp_predict(stem_mlp_t mlp, const float* x, int32_t n, float* y, void* stream);
+stem_status stem_mlp_destroy(stem_mlp_t mlp);
 
 /*
  * Fill dst (device, n complex64) with the counter-based test tensor: entry i

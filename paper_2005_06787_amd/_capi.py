@@ -57,6 +57,10 @@ class stem_step_info(ctypes.Structure):
         ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
         ("perm_bytes", ctypes.c_double),
         ("last_gemm_us", ctypes.c_float), ("last_perm_us", ctypes.c_float),
+        ("amode", ctypes.c_int32), ("cmode", ctypes.c_int32),
+        ("sched_tm", ctypes.c_int32), ("sched_ntw", ctypes.c_int32),
+        ("sched_blocks", ctypes.c_int32), ("sched_lds", ctypes.c_int32),
+        ("tuned_us", ctypes.c_float), ("tuned_slices", ctypes.c_int32),
     ]
 
 
@@ -69,8 +73,42 @@ class stem_plan_summary(ctypes.Structure):
     ]
 
 
+class stem_hw(ctypes.Structure):
+    _fields_ = [
+        ("hbm_bytes_per_s", ctypes.c_double), ("fp32_flops_per_s", ctypes.c_double),
+        ("fp16_flops_per_s", ctypes.c_double), ("launch_s", ctypes.c_double),
+    ]
+
+
+STEM_N_FEATURES = 12
+_f32p_ = ctypes.POINTER(ctypes.c_float)
+
 # name -> (restype, argtypes); every function declared in include/stemgpu.h
 SIGNATURES = {
+    "stem_plan_steps": (ctypes.c_int32, [ctypes.POINTER(stem_plan_desc),
+                                         ctypes.POINTER(stem_step_info), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "stem_cost_analytic": (ctypes.c_int32, [ctypes.POINTER(stem_step_info), ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                                            ctypes.POINTER(stem_hw),
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "stem_step_features": (ctypes.c_int32, [ctypes.POINTER(stem_step_info), ctypes.c_int32,
+                                            ctypes.c_uint32, _f32p_]),
+    "stem_mlp_n_params": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32]),
+    "stem_mlp_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _f32p_,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "stem_mlp_set_scaling": (ctypes.c_int32, [ctypes.c_void_p, _f32p_, _f32p_, ctypes.c_float,
+                                              ctypes.c_float]),
+    "stem_mlp_get_params": (ctypes.c_int32, [ctypes.c_void_p, _f32p_]),
+    "stem_mlp_loss_grad": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
+    "stem_mlp_train": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "stem_mlp_predict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "stem_mlp_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "stem_plan_validate": (ctypes.c_int32, [ctypes.POINTER(stem_plan_desc),
                                             ctypes.POINTER(stem_plan_summary)]),
     "stem_plan_create": (ctypes.c_int32, [ctypes.POINTER(stem_plan_desc), ctypes.c_void_p,
@@ -86,6 +124,9 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32,
                                        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                        ctypes.c_uint32, ctypes.c_void_p]),
+    "stem_tune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.c_uint64, ctypes.c_int32, ctypes.c_char_p,
+                                   ctypes.c_void_p]),
     "stem_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.POINTER(ctypes.c_uint64),
                                            ctypes.POINTER(ctypes.c_uint64),

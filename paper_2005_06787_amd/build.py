@@ -1,7 +1,8 @@
 """Build libstemgpu.so (the HIP kernels and the C-ABI) in-tree for gfx950.
 
 Usage: python -m paper_2005_06787_amd.build   (or call build()).
-The library lands in paper_2005_06787_amd/_lib/libstemgpu.so.
+The library lands in paper_2005_06787_amd/_lib/libstemgpu.so.  Sources are
+compiled in parallel (one hipcc process each), then linked.
 """
 
 from __future__ import annotations
@@ -9,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -16,7 +18,8 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libstemgpu.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["kernels.hip", "api.hip", "plan.cpp"]
+SOURCES = ["gemm_f32.hip", "gemm_split.hip", "kernels.hip", "api.hip", "mlp.hip", "plan.cpp",
+           "cost.cpp"]
 
 # Packed FP32 instructions are kept out of every kernel: only scalar FP32
 # vector ops and the MFMA instructions are emitted.
@@ -33,25 +36,30 @@ def _hipcc() -> str:
     return "hipcc"
 
 
+def _compile(src: str, objdir: str, verbose: bool) -> str:
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(objdir, src + ".o")
+    if src.endswith(".cpp"):
+        cmd = [_hipcc(), "-O2", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,
+               "-c", path, "-o", obj]
+    else:
+        cmd = [_hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(objdir, src + ".o")
-        cmd = [_hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [_hipcc(), "-O2", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,
-                   "-c", path, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        if res.returncode != 0:
-            sys.stderr.write(res.stdout + res.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
-        objs.append(obj)
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        objs = list(pool.map(lambda s: _compile(s, objdir, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -7,8 +7,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.h"
@@ -39,6 +42,8 @@ struct stem_plan_s {
   std::vector<StepDev> sd;
   std::vector<hipEvent_t> ev;       // 4 per step when timing: perm start/end, gemm start/end
   std::vector<float> gemm_us, perm_us;
+  std::vector<float> tuned_us;      // per step, from stem_tune
+  std::vector<int> tuned_nz;
   int timed_slices = 0;
   bool timed_pending = false;
 };
@@ -210,6 +215,8 @@ static stem_status plan_create_impl(const stem_plan_desc* d, hipStream_t st, ste
   HIPCHK(hipStreamSynchronize(st));
   p->gemm_us.assign(L.steps.size(), -1.f);
   p->perm_us.assign(L.steps.size(), -1.f);
+  p->tuned_us.assign(L.steps.size(), -1.f);
+  p->tuned_nz.assign(L.steps.size(), 0);
   return STEM_OK;
 }
 
@@ -260,11 +267,10 @@ stem_status stem_plan_workspace_bytes(stem_plan_t plan, uint32_t slices_in_fligh
   return STEM_OK;
 }
 
-stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* info) {
-  if (!plan || !info) return fail(STEM_EINVAL, "null argument");
-  if (step < 0 || step >= (int32_t)plan->L.steps.size())
-    return fail(STEM_ERANGE, "step index out of range");
-  const StepLayout& S = plan->L.steps[step];
+}  // extern "C"
+
+// Shape, cost and layout fields of a step (timing fields -1).
+static void fill_info(const StepLayout& S, stem_step_info* info) {
   std::memset(info, 0, sizeof(*info));
   info->rank_in = S.rank_in;
   info->rank_out = S.rank_out;
@@ -278,6 +284,43 @@ stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* i
   info->flops = 8.0 * M * K * N;
   info->bytes = 8.0 * (M * K + M * N + K * N);
   info->perm_bytes = S.permuted ? 16.0 * (double)(1ull << S.rank_in) : 0.0;
+  info->last_gemm_us = -1.f;
+  info->last_perm_us = -1.f;
+  info->amode = S.gemm.amode;
+  info->cmode = S.gemm.cmode;
+  info->sched_tm = S.sched.tm;
+  info->sched_ntw = S.sched.ntw;
+  info->sched_blocks = S.sched.blocks;
+  info->sched_lds = S.sched.lds;
+  info->tuned_us = -1.f;
+}
+
+extern "C" {
+
+stem_status stem_plan_steps(const stem_plan_desc* desc, stem_step_info* steps, int32_t capacity,
+                            int32_t* n_steps) {
+  if (!n_steps || capacity < 0 || (capacity && !steps)) return fail(STEM_EINVAL, "null argument");
+  try {
+    PlanLayout L;
+    std::string err;
+    stem_status s = build_layout(desc, &L, &err);
+    if (s != STEM_OK) return fail(s, err);
+    *n_steps = (int32_t)L.steps.size();
+    for (int32_t i = 0; i < std::min(capacity, *n_steps); ++i) fill_info(L.steps[i], &steps[i]);
+    return STEM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(STEM_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(STEM_EINVAL, "unexpected host exception");
+  }
+}
+
+stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* info) {
+  if (!plan || !info) return fail(STEM_EINVAL, "null argument");
+  if (step < 0 || step >= (int32_t)plan->L.steps.size())
+    return fail(STEM_ERANGE, "step index out of range");
+  const StepLayout& S = plan->L.steps[step];
+  fill_info(S, info);
   if (plan->timed_pending) {
     // resolve the events of the last timed call (the caller synchronised)
     for (size_t i = 0; i < plan->L.steps.size(); ++i) {
@@ -293,7 +336,159 @@ stem_status stem_step_info_get(stem_plan_t plan, int32_t step, stem_step_info* i
   info->last_slices = plan->timed_slices;
   info->last_gemm_us = plan->gemm_us[step];
   info->last_perm_us = plan->perm_us[step];
+  info->tuned_us = plan->tuned_us[step];
+  info->tuned_slices = plan->tuned_nz[step];
   return STEM_OK;
+}
+
+}  // extern "C"
+
+// ---- autotuner -------------------------------------------------------------
+
+namespace {
+
+struct TuneKey {
+  int prec, amode, cmode, lm, lk, ln, nz;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, amode, cmode, lm, lk, ln, nz) <
+           std::tie(o.prec, o.amode, o.cmode, o.lm, o.lk, o.ln, o.nz);
+  }
+};
+
+struct TuneBest {
+  GemmSched sched;
+  float us = 1e30f;
+};
+
+int ilog2(int64_t v) {
+  int r = 0;
+  while ((1ll << r) < v) ++r;
+  return r;
+}
+
+void load_cache(const char* path, std::map<TuneKey, TuneBest>* best) {
+  if (!path) return;
+  std::ifstream f(path);
+  std::string tag;
+  while (f >> tag) {
+    TuneKey k;
+    GemmSched s;
+    float us;
+    if (tag != "stem-tune-v1" || !(f >> k.prec >> k.amode >> k.cmode >> k.lm >> k.lk >> k.ln >>
+                                   k.nz >> s.tm >> s.ntw >> s.blocks >> s.lds >> us)) {
+      std::string rest;
+      std::getline(f, rest);
+      continue;
+    }
+    TuneBest& b = (*best)[k];
+    if (us < b.us) {
+      b.us = us;
+      b.sched = s;
+    }
+  }
+}
+
+// Candidate schedules of one step (distinct after the kernel's own clamping).
+std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
+  const int nr = (int)(2 * S.N);
+  const int nt = std::max(16, nr) / 16;
+  int nt2 = 1;
+  while (nt2 < nt) nt2 <<= 1;
+  std::vector<int> ntws;
+  for (int w : {8, 4, 2, 1})
+    if (w <= nt2 && (w == std::min(8, nt2) || w * 2 == std::min(8, nt2))) ntws.push_back(w);
+  const int kq = precision == STEM_FP32 ? 16 : 32;
+  const int kc = std::max<int>(kq, (int)(2 * S.K)) / kq;
+  std::vector<GemmSched> out;
+  for (int tm : {1, 2, 4})
+    for (int w : ntws)
+      for (int blocks : {1024, 4096, 16384}) {
+        const size_t lds = precision == STEM_FP32 ? (size_t)kc * w * 1024 : (size_t)kc * w * 2048;
+        for (int l : {-1, 0}) {
+          if (l == 0 && lds > 64 * 1024) continue;  // already global
+          GemmSched s;
+          s.tm = tm;
+          s.ntw = w;
+          s.blocks = blocks;
+          s.lds = l;
+          out.push_back(s);
+        }
+      }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, int32_t reps,
+                      const char* cache_path, void* stream) {
+  if (!p) return fail(STEM_EINVAL, "null plan");
+  hipStream_t st = (hipStream_t)stream;
+  const PlanLayout& L = p->L;
+  if (L.steps.empty()) return STEM_OK;
+  if (nz < 1 || nz > (uint32_t)kMaxSlicesInFlight) return fail(STEM_ERANGE, "slices_in_flight");
+  const uint64_t per = slice_ws_bytes(p);
+  if (!ws || ws_bytes < per * nz)
+    return fail(STEM_ENOMEM, "workspace smaller than stem_plan_workspace_bytes(plan, slices)");
+  const bool force = reps < 0;
+  const int nrep = std::max(1, reps < 0 ? -reps : reps);
+  std::map<TuneKey, TuneBest> best;
+  load_cache(cache_path, &best);
+  std::ofstream log;
+  if (cache_path) log.open(cache_path, std::ios::app);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int64_t half = (int64_t)(per / 2);
+  const Operand in = plain_operand(ws, half);
+  const Operand out = plain_operand((unsigned char*)ws + half * (int64_t)nz, half);
+  stem_status rs = STEM_OK;
+  for (size_t i = 0; i < L.steps.size() && rs == STEM_OK; ++i) {
+    StepLayout& S = p->L.steps[i];
+    const TuneKey key{p->precision, S.gemm.amode, S.gemm.cmode, ilog2(S.M), ilog2(S.K),
+                      ilog2(S.N), (int)nz};
+    auto it = best.find(key);
+    if (!force && it != best.end()) {
+      S.sched = it->second.sched;
+      p->tuned_us[i] = it->second.us;
+      p->tuned_nz[i] = (int)nz;
+      continue;
+    }
+    const Operand bop = plain_operand(p->d_branch + p->sd[i].boff, 0);
+    TuneBest win;
+    for (const GemmSched& c : candidates(S, p->precision)) {
+      hipError_t e = launch_cgemm(p->precision, in, bop, out, 0, (int)nz, S.M, S.K, S.N, S.gemm, c, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < nrep && e == hipSuccess; ++r)
+        e = launch_cgemm(p->precision, in, bop, out, 0, (int)nz, S.M, S.K, S.N, S.gemm, c, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rs = fail(STEM_EHIP, std::string("tuning launch: ") + hipGetErrorString(e));
+        break;
+      }
+      const float us = ms * 1000.f / (float)nrep;
+      if (log.is_open())
+        log << "stem-tune-v1 " << key.prec << ' ' << key.amode << ' ' << key.cmode << ' '
+            << key.lm << ' ' << key.lk << ' ' << key.ln << ' ' << key.nz << ' ' << c.tm << ' '
+            << c.ntw << ' ' << c.blocks << ' ' << c.lds << ' ' << us << '\n';
+      if (us < win.us) {
+        win.us = us;
+        win.sched = c;
+      }
+    }
+    if (rs != STEM_OK) break;
+    if (it == best.end() || win.us < it->second.us) best[key] = win;
+    S.sched = best[key].sched;
+    p->tuned_us[i] = best[key].us;
+    p->tuned_nz[i] = (int)nz;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rs;
 }
 
 }  // extern "C"
@@ -458,7 +653,9 @@ stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_
     return s;
   };
   if (hipGetDevice(&b->device) != hipSuccess) return bail(fail(STEM_EHIP, "hipGetDevice failed"));
-  b->side.resize(n, nullptr);
+  // Recording happens on a private stream (the caller's may be the null
+  // stream, which cannot be captured); side[n] is that stream.
+  b->side.resize(n + 1, nullptr);
   b->events.resize(n + 1, nullptr);
   for (auto& s : b->side)
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
@@ -466,6 +663,8 @@ stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_
   for (auto& e : b->events)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
       return bail(fail(STEM_EHIP, "hipEventCreate failed"));
+  (void)stream;
+  st = b->side[n];
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return bail(fail(STEM_EHIP, std::string("begin capture: ") + hipGetErrorString(e)));
   stem_status rs = batch_record(b, n, plans, s0, s1, proj, out, (unsigned char*)ws, part, flags, st);

@@ -1,0 +1,204 @@
+// Device helpers shared by the libstemgpu kernels (gfx950): operand
+// selection per slice, the product's operand addressing, launch geometry.
+// Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace stem {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kLdsBudget = 64 * 1024;  // branch fragments staged in LDS up to this size
+constexpr int kTargetBlocks = 4096;    // workgroups per launch before row loops kick in
+
+// Loops over the small per-launch tables below are fully unrolled with a
+// predicate, so every table index is a constant and the tables stay in
+// scalar registers instead of being copied into per-lane arrays.
+__device__ __forceinline__ const char* op_base(const Operand& o, int z, uint64_t s0) {
+  uint64_t v = o.sel.vbase;
+  const uint64_t s = s0 + (uint64_t)z;
+#pragma unroll
+  for (int j = 0; j < kMaxSlicedPerTensor; ++j)
+    if (j < o.sel.nv) v |= ((s >> o.sel.vshift[j]) & 1ull) << o.sel.vpos[j];
+  return (const char*)o.ptr + (int64_t)z * o.zstride + (int64_t)v * o.vstride;
+}
+
+// ---------------------------------------------------------------------------
+// Complex product C[M x N] = A[M x K] . B[K x N] of one stem step.
+//
+// Operand addressing (GemmLayout).  A is the stem: row m starts at
+// lo(m & 15) | spread(m >> 4) and entry k sits kpos(k) further, so any
+// order of the stem's labels is read in place:
+//   K-low (AM = 0): k bits 0..2 are the 3 fastest address bits; lane group
+//                   g reads k = 2g, 2g+1 of its row as one 16-byte vector
+//                   and the 4 groups cover 64 contiguous bytes of the row;
+//   M-fast (AM = 1): the 4 low bits of m are the 4 fastest address bits, so
+//                   the 16 rows of a block are 128 contiguous bytes per k.
+// C is the next stem: entry (m, n) goes to
+//   N-fast (CM = 0): m N + n                           (when M < 16)
+//   CM = 1:          (m>>4) 2^(4+f) | n 2^4 | (m&15)   (the 4 labels of m's
+//                   low bits become the output's fastest, new labels above)
+// so the next step can read the output M-fast, and the host chooses which
+// 4 labels sit at the bottom without a separate permute pass.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t row_base(int64_t m, const GemmGeom& g) {
+  int64_t lo = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) lo |= ((m >> b) & 1ll) << g.mlo[b];
+  int64_t a = m >> 4;
+#pragma unroll
+  for (int i = 0; i < kMaxShared + 4; ++i) {
+    if (i < g.nins) {
+      const int p = g.ins[i];
+      a = ((a >> p) << (p + 1)) | (a & ((1ll << p) - 1));
+    }
+  }
+  return a | lo;
+}
+
+__device__ __forceinline__ int64_t k_offset(int k, const GemmGeom& g) {
+  int64_t a = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxShared; ++i)
+    if (i < g.s) a |= (int64_t)((k >> i) & 1) << g.spos[i];
+  return a;
+}
+
+// 4 consecutive reals A[m][kr0 .. kr0+3] (= complex k0 = kr0/2 and k0+1);
+// ko0/ko1 are the offsets of those two k values (adjacent in K-low mode).
+template <int AM>
+__device__ __forceinline__ f32x4 load_kr4(const float* __restrict__ A, int64_t rb, int kr0,
+                                          int64_t ko0, int64_t ko1, const GemmGeom& g) {
+  f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (rb < 0) return v;
+  if (AM == 0) {
+    if (kr0 < g.Kr) {
+      const float* src = A + 2 * (rb + ko0);
+      if (g.Kr >= 4) {
+        v = *(const f32x4*)src;
+      } else {
+        const float2 t = *(const float2*)src;
+        v.x = t.x;
+        v.y = t.y;
+      }
+    }
+  } else {
+    const int k0 = kr0 >> 1;
+    if (k0 < g.K) {
+      const float2 t = *(const float2*)(A + 2 * (rb + ko0));
+      v.x = t.x;
+      v.y = t.y;
+    }
+    if (k0 + 1 < g.K) {
+      const float2 t = *(const float2*)(A + 2 * (rb + ko1));
+      v.z = t.x;
+      v.w = t.y;
+    }
+  }
+  return v;
+}
+
+// Store the 4 consecutive reals C[m][nr0 .. nr0+3].
+template <int CM>
+__device__ __forceinline__ void store_nr4(float* __restrict__ C, int64_t m, int nr0, f32x4 v,
+                                          const GemmGeom& g) {
+  if (CM == 0) {
+    if (nr0 >= g.Nr) return;
+    float* dst = C + m * (int64_t)g.Nr + nr0;
+    if (g.Nr >= 4)
+      *(f32x4*)dst = v;
+    else
+      *(float2*)dst = float2{v.x, v.y};
+  } else {
+    const int n0 = nr0 >> 1;
+    const int64_t base = ((m >> 4) << (4 + g.f)) | (m & 15);
+    if (n0 < g.N) *(float2*)(C + 2 * (base | ((int64_t)n0 << 4))) = float2{v.x, v.y};
+    if (n0 + 1 < g.N) *(float2*)(C + 2 * (base | ((int64_t)(n0 + 1) << 4))) = float2{v.z, v.w};
+  }
+}
+
+static inline GemmGeom make_geom(const GemmLayout& lay, int64_t M, int64_t K, int64_t N, int kq) {
+  GemmGeom g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = M;
+  g.K = (int)K;
+  g.N = (int)N;
+  g.Kr = (int)(2 * K);
+  g.Nr = (int)(2 * N);
+  g.KC = std::max(kq, g.Kr) / kq;
+  g.NT = std::max(16, g.Nr) / 16;
+  g.s = lay.s;
+  g.f = lay.f;
+  for (int i = 0; i < 16; ++i) g.spos[i] = lay.spos[i];
+  for (int i = 0; i < 4; ++i) g.mlo[i] = lay.mlo[i];
+  g.nins = lay.nins;
+  for (int i = 0; i < 20; ++i) g.ins[i] = lay.ins[i];
+  return g;
+}
+
+// Schedule with the defaults filled in (see GemmSched).
+static inline GemmSched resolve_sched(const GemmGeom& g, GemmSched s) {
+  int nt2 = 1;
+  while (nt2 < g.NT) nt2 <<= 1;
+  if (s.ntw <= 0) s.ntw = std::min(8, nt2);
+  s.ntw = std::min(s.ntw, std::min(8, nt2));
+  if (s.tm <= 0) s.tm = s.ntw <= 2 ? 4 : 2;
+  if (s.blocks <= 0) s.blocks = kTargetBlocks;
+  return s;
+}
+
+// Grid of a product launch: x row-block groups (each workgroup loops over
+// row blocks when there are more than the target), y column chunks, z slices.
+static inline dim3 gemm_grid(const GemmGeom& g, int TM, int NTW, int nz, int target) {
+  const int64_t rows_per_wg = 4 * 16 * TM;
+  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
+  const int gy = (g.NT + NTW - 1) / NTW;
+  const int64_t want = std::max<int64_t>(1, target / ((int64_t)gy * nz));
+  const int64_t gx = std::min<int64_t>(nblk, want);
+  return dim3((unsigned)gx, (unsigned)gy, (unsigned)nz);
+}
+
+struct LaunchCtx {
+  const Operand* A;
+  const Operand* B;
+  const Operand* C;
+  uint64_t s0;
+  int nz;
+  GemmGeom g;
+  GemmSched sch;
+  hipStream_t st;
+};
+
+#define STEM_TM_NTW_DISPATCH(FN, ...)                                        \
+  switch (c.sch.tm * 16 + c.sch.ntw) {                                       \
+    case 16 + 1: FN<1, 1, __VA_ARGS__>(c); break;                            \
+    case 16 + 2: FN<1, 2, __VA_ARGS__>(c); break;                            \
+    case 16 + 4: FN<1, 4, __VA_ARGS__>(c); break;                            \
+    case 16 + 8: FN<1, 8, __VA_ARGS__>(c); break;                            \
+    case 32 + 1: FN<2, 1, __VA_ARGS__>(c); break;                            \
+    case 32 + 2: FN<2, 2, __VA_ARGS__>(c); break;                            \
+    case 32 + 4: FN<2, 4, __VA_ARGS__>(c); break;                            \
+    case 32 + 8: FN<2, 8, __VA_ARGS__>(c); break;                            \
+    case 64 + 1: FN<4, 1, __VA_ARGS__>(c); break;                            \
+    case 64 + 2: FN<4, 2, __VA_ARGS__>(c); break;                            \
+    case 64 + 4: FN<4, 4, __VA_ARGS__>(c); break;                            \
+    default: FN<4, 8, __VA_ARGS__>(c); break;                                \
+  }
+
+
+// Product launchers, one translation unit per arithmetic.
+void launch_gemm_f32(const LaunchCtx& c, const GemmLayout& lay);
+void launch_gemm_split(const LaunchCtx& c, const GemmLayout& lay, int bf16);
+
+}  // namespace stem

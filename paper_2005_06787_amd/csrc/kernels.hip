@@ -14,29 +14,9 @@
 #include <cmath>
 #include <cstring>
 
-#include "kernels.h"
+#include "device_common.h"
 
 namespace stem {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int kLdsBudget = 64 * 1024;  // branch fragments staged in LDS up to this size
-constexpr int kTargetBlocks = 4096;    // workgroups per launch before row loops kick in
-
-// Loops over the small per-launch tables below are fully unrolled with a
-// predicate, so every table index is a constant and the tables stay in
-// scalar registers instead of being copied into per-lane arrays.
-__device__ __forceinline__ const char* op_base(const Operand& o, int z, uint64_t s0) {
-  uint64_t v = o.sel.vbase;
-  const uint64_t s = s0 + (uint64_t)z;
-#pragma unroll
-  for (int j = 0; j < kMaxSlicedPerTensor; ++j)
-    if (j < o.sel.nv) v |= ((s >> o.sel.vshift[j]) & 1ull) << o.sel.vpos[j];
-  return (const char*)o.ptr + (int64_t)z * o.zstride + (int64_t)v * o.vstride;
-}
 
 // ---------------------------------------------------------------------------
 // Bit-permutation transpose, staged through LDS.
@@ -90,208 +70,6 @@ hipError_t launch_permute(const Operand& in, const Operand& out, const PermArgs&
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Complex product C[M x N] = A[M x K] . B[K x N] of one stem step.
-//
-// Operand addressing (GemmLayout).  A is the stem: row m starts at
-// lo(m & 15) | spread(m >> 4) and entry k sits kpos(k) further, so any
-// order of the stem's labels is read in place:
-//   K-low (AM = 0): k bits 0..2 are the 3 fastest address bits; lane group
-//                   g reads k = 2g, 2g+1 of its row as one 16-byte vector
-//                   and the 4 groups cover 64 contiguous bytes of the row;
-//   M-fast (AM = 1): the 4 low bits of m are the 4 fastest address bits, so
-//                   the 16 rows of a block are 128 contiguous bytes per k.
-// C is the next stem: entry (m, n) goes to
-//   N-fast (CM = 0): m N + n                           (when M < 16)
-//   CM = 1:          (m>>4) 2^(4+f) | n 2^4 | (m&15)   (the 4 labels of m's
-//                   low bits become the output's fastest, new labels above)
-// so the next step can read the output M-fast, and the host chooses which
-// 4 labels sit at the bottom without a separate permute pass.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int64_t row_base(int64_t m, const GemmGeom& g) {
-  int64_t lo = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) lo |= ((m >> b) & 1ll) << g.mlo[b];
-  int64_t a = m >> 4;
-#pragma unroll
-  for (int i = 0; i < kMaxShared + 4; ++i) {
-    if (i < g.nins) {
-      const int p = g.ins[i];
-      a = ((a >> p) << (p + 1)) | (a & ((1ll << p) - 1));
-    }
-  }
-  return a | lo;
-}
-
-__device__ __forceinline__ int64_t k_offset(int k, const GemmGeom& g) {
-  int64_t a = 0;
-#pragma unroll
-  for (int i = 0; i < kMaxShared; ++i)
-    if (i < g.s) a |= (int64_t)((k >> i) & 1) << g.spos[i];
-  return a;
-}
-
-// 4 consecutive reals A[m][kr0 .. kr0+3] (= complex k0 = kr0/2 and k0+1);
-// ko0/ko1 are the offsets of those two k values (adjacent in K-low mode).
-template <int AM>
-__device__ __forceinline__ f32x4 load_kr4(const float* __restrict__ A, int64_t rb, int kr0,
-                                          int64_t ko0, int64_t ko1, const GemmGeom& g) {
-  f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (rb < 0) return v;
-  if (AM == 0) {
-    if (kr0 < g.Kr) {
-      const float* src = A + 2 * (rb + ko0);
-      if (g.Kr >= 4) {
-        v = *(const f32x4*)src;
-      } else {
-        const float2 t = *(const float2*)src;
-        v.x = t.x;
-        v.y = t.y;
-      }
-    }
-  } else {
-    const int k0 = kr0 >> 1;
-    if (k0 < g.K) {
-      const float2 t = *(const float2*)(A + 2 * (rb + ko0));
-      v.x = t.x;
-      v.y = t.y;
-    }
-    if (k0 + 1 < g.K) {
-      const float2 t = *(const float2*)(A + 2 * (rb + ko1));
-      v.z = t.x;
-      v.w = t.y;
-    }
-  }
-  return v;
-}
-
-// Store the 4 consecutive reals C[m][nr0 .. nr0+3].
-template <int CM>
-__device__ __forceinline__ void store_nr4(float* __restrict__ C, int64_t m, int nr0, f32x4 v,
-                                          const GemmGeom& g) {
-  if (CM == 0) {
-    if (nr0 >= g.Nr) return;
-    float* dst = C + m * (int64_t)g.Nr + nr0;
-    if (g.Nr >= 4)
-      *(f32x4*)dst = v;
-    else
-      *(float2*)dst = float2{v.x, v.y};
-  } else {
-    const int n0 = nr0 >> 1;
-    const int64_t base = ((m >> 4) << (4 + g.f)) | (m & 15);
-    if (n0 < g.N) *(float2*)(C + 2 * (base | ((int64_t)n0 << 4))) = float2{v.x, v.y};
-    if (n0 + 1 < g.N) *(float2*)(C + 2 * (base | ((int64_t)(n0 + 1) << 4))) = float2{v.z, v.w};
-  }
-}
-
-// ---------------------------------------------------------------------------
-// FP32 product on the 16x16x4 f32 MFMA.
-//
-// The kernel computes the transposed product C^T = B'^T A^T so that the
-// (possibly narrow) 2N real output columns sit on the MFMA's row side and
-// the long M side on its column side: lane l owns stem row m = l%16 of a
-// 16-row block, and its accumulator holds the 4 consecutive real outputs
-// C[m][16 nt + 4 (l/16) + r], r = 0..3.  Summation order inside a 16-wide
-// real k chunk is free, so lane group g = l/16 holds the 4 consecutive reals
-// A[m][16 kc + 4 g .. +3] and feeds element j to MFMA number j; the branch
-// fragments were laid out on the host in the same k order.
-//
-// Each wave handles TM 16-row blocks (every branch fragment is reused TM
-// times) and NTW 16-column tiles; blockIdx.y splits wide outputs.  With
-// BLDS the workgroup first copies its branch fragments into LDS; the
-// workgroups then loop over the row blocks.
-// ---------------------------------------------------------------------------
-template <int TM, int NTW, int AM, int CM, int BLDS>
-__global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand Bo, Operand Co,
-                                                             uint64_t s0, GemmGeom g) {
-  extern __shared__ __align__(16) float sB[];
-  const int z = blockIdx.z;
-  const float* __restrict__ A = (const float*)op_base(Ao, z, s0);
-  const float* __restrict__ Bf = (const float*)(op_base(Bo, z, s0) + kBranchHeader);
-  float* __restrict__ C = (float*)op_base(Co, z, s0);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int grp = lane >> 4;
-  const int r16 = lane & 15;
-  const int nt0 = blockIdx.y * NTW;
-  const int ntw = min(NTW, g.NT - nt0);
-
-  if (BLDS) {
-    const int per_kc = ntw * 256;
-    for (int i = threadIdx.x * 4; i < g.KC * per_kc; i += 1024) {
-      const int kc = i / per_kc, r = i - kc * per_kc;
-      *(f32x4*)(sB + kc * NTW * 256 + r) = *(const f32x4*)(Bf + (size_t)(kc * g.NT + nt0) * 256 + r);
-    }
-    __syncthreads();
-  }
-
-  const int64_t rows_per_wg = 4 * 16 * TM;
-  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
-    if (row0 >= g.M) continue;
-    f32x4 acc[TM][NTW];
-    int64_t rb[TM];
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      rb[t] = row < g.M ? row_base(row, g) : -1;
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    f32x4 a[TM];
-    {
-      const int kr0 = grp * 4;
-      const int64_t ko0 = k_offset(kr0 >> 1, g);
-      const int64_t ko1 = AM == 1 ? k_offset((kr0 >> 1) + 1, g) : 0;
-#pragma unroll
-      for (int t = 0; t < TM; ++t) a[t] = load_kr4<AM>(A, rb[t], kr0, ko0, ko1, g);
-    }
-    for (int kc = 0; kc < g.KC; ++kc) {
-      // prefetch the next k chunk of A while this one is multiplied
-      f32x4 an[TM];
-      if (kc + 1 < g.KC) {
-        const int kr1 = (kc + 1) * 16 + grp * 4;
-        const int64_t ko0 = k_offset(kr1 >> 1, g);
-        const int64_t ko1 = AM == 1 ? k_offset((kr1 >> 1) + 1, g) : 0;
-#pragma unroll
-        for (int t = 0; t < TM; ++t) an[t] = load_kr4<AM>(A, rb[t], kr1, ko0, ko1, g);
-      }
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) {
-        if (n < ntw) {
-          float b[4];
-          if (BLDS) {
-            const float* bp = sB + (kc * NTW + n) * 256 + lane;
-            b[0] = bp[0]; b[1] = bp[64]; b[2] = bp[128]; b[3] = bp[192];
-          } else {
-            const float* bp = Bf + ((size_t)(kc * g.NT + nt0 + n) * 4) * 64 + lane;
-            b[0] = bp[0]; b[1] = bp[64]; b[2] = bp[128]; b[3] = bp[192];
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int t = 0; t < TM; ++t)
-              acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[t][j], acc[t][n], 0, 0, 0);
-        }
-      }
-      if (kc + 1 < g.KC) {
-#pragma unroll
-        for (int t = 0; t < TM; ++t) a[t] = an[t];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      if (row >= g.M) continue;
-#pragma unroll
-      for (int n = 0; n < NTW; ++n)
-        if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n], g);
-    }
-  }
-}
-
 size_t bfrag_f32_floats(int64_t K, int64_t N) {
   const int64_t Kp = std::max<int64_t>(16, 2 * K), Np = std::max<int64_t>(16, 2 * N);
   return (size_t)(Kp * Np);
@@ -328,261 +106,6 @@ void build_bfrag_f32(const float* b, int64_t K, int64_t N, float* out) {
           const int64_t nr = 16 * nt + (lane & 15);
           out[((kc * NT + nt) * 4 + j) * 64 + lane] = expanded(b, K, N, kr, nr);
         }
-}
-
-static GemmGeom make_geom(const GemmLayout& lay, int64_t M, int64_t K, int64_t N, int kq) {
-  GemmGeom g;
-  std::memset(&g, 0, sizeof(g));
-  g.M = M;
-  g.K = (int)K;
-  g.N = (int)N;
-  g.Kr = (int)(2 * K);
-  g.Nr = (int)(2 * N);
-  g.KC = std::max(kq, g.Kr) / kq;
-  g.NT = std::max(16, g.Nr) / 16;
-  g.s = lay.s;
-  g.f = lay.f;
-  for (int i = 0; i < 16; ++i) g.spos[i] = lay.spos[i];
-  for (int i = 0; i < 4; ++i) g.mlo[i] = lay.mlo[i];
-  g.nins = lay.nins;
-  for (int i = 0; i < 20; ++i) g.ins[i] = lay.ins[i];
-  return g;
-}
-
-// Schedule with the defaults filled in (see GemmSched).
-static GemmSched resolve_sched(const GemmGeom& g, GemmSched s) {
-  int nt2 = 1;
-  while (nt2 < g.NT) nt2 <<= 1;
-  if (s.ntw <= 0) s.ntw = std::min(8, nt2);
-  s.ntw = std::min(s.ntw, std::min(8, nt2));
-  if (s.tm <= 0) s.tm = s.ntw <= 2 ? 4 : 2;
-  if (s.blocks <= 0) s.blocks = kTargetBlocks;
-  return s;
-}
-
-// Grid of a product launch: x row-block groups (each workgroup loops over
-// row blocks when there are more than the target), y column chunks, z slices.
-static dim3 gemm_grid(const GemmGeom& g, int TM, int NTW, int nz, int target) {
-  const int64_t rows_per_wg = 4 * 16 * TM;
-  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
-  const int gy = (g.NT + NTW - 1) / NTW;
-  const int64_t want = std::max<int64_t>(1, target / ((int64_t)gy * nz));
-  const int64_t gx = std::min<int64_t>(nblk, want);
-  return dim3((unsigned)gx, (unsigned)gy, (unsigned)nz);
-}
-
-struct LaunchCtx {
-  const Operand* A;
-  const Operand* B;
-  const Operand* C;
-  uint64_t s0;
-  int nz;
-  GemmGeom g;
-  GemmSched sch;
-  hipStream_t st;
-};
-
-template <int TM, int NTW, int AM, int CM>
-static void launch_f32_t(const LaunchCtx& c) {
-  const dim3 grid = gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks);
-  const size_t lds = (size_t)c.g.KC * NTW * 256 * 4;
-  if (lds <= (size_t)kLdsBudget && c.sch.lds != 0)
-    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1>), grid, dim3(256), lds, c.st,
-                       *c.A, *c.B, *c.C, c.s0, c.g);
-  else
-    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 0>), grid, dim3(256), 0, c.st,
-                       *c.A, *c.B, *c.C, c.s0, c.g);
-}
-
-#define STEM_TM_NTW_DISPATCH(FN, ...)                                        \
-  switch (c.sch.tm * 16 + c.sch.ntw) {                                       \
-    case 16 + 1: FN<1, 1, __VA_ARGS__>(c); break;                            \
-    case 16 + 2: FN<1, 2, __VA_ARGS__>(c); break;                            \
-    case 16 + 4: FN<1, 4, __VA_ARGS__>(c); break;                            \
-    case 16 + 8: FN<1, 8, __VA_ARGS__>(c); break;                            \
-    case 32 + 1: FN<2, 1, __VA_ARGS__>(c); break;                            \
-    case 32 + 2: FN<2, 2, __VA_ARGS__>(c); break;                            \
-    case 32 + 4: FN<2, 4, __VA_ARGS__>(c); break;                            \
-    case 32 + 8: FN<2, 8, __VA_ARGS__>(c); break;                            \
-    case 64 + 1: FN<4, 1, __VA_ARGS__>(c); break;                            \
-    case 64 + 2: FN<4, 2, __VA_ARGS__>(c); break;                            \
-    case 64 + 4: FN<4, 4, __VA_ARGS__>(c); break;                            \
-    default: FN<4, 8, __VA_ARGS__>(c); break;                                \
-  }
-
-template <int AM, int CM>
-static void launch_f32_m(const LaunchCtx& c) {
-  STEM_TM_NTW_DISPATCH(launch_f32_t, AM, CM)
-}
-
-// ---------------------------------------------------------------------------
-// Three-term split product on the 16x16x32 f16 / bf16 MFMA, FP32 accumulate.
-//
-// x = hi + lo with hi = round(x 2^e), lo = round(x 2^e - hi); the product
-// keeps hi*hi + hi*lo + lo*hi and drops lo*lo (Markidis et al. 2018, the
-// mixed-precision refinement the paper points to for tensor cores).  For
-// FP16 every stem row gets its own power-of-two scale 2^e per 32-wide real
-// k chunk, from the row's largest magnitude in the chunk, so that the row's
-// largest entry lands in [2^13, 2^14); the chunk's partial product is then
-// scaled back by 2^-e before it joins the FP32 accumulator.  BF16 has
-// FP32's range and uses e = 0.  The branch was split and scaled (2^eb) on
-// the host; 2^-eb sits in the variant's header.  Lane layout as in the FP32
-// kernel with 8 consecutive reals of k per lane group.
-// ---------------------------------------------------------------------------
-template <int BF16>
-struct SplitT;
-template <>
-struct SplitT<0> {
-  typedef f16x8 vec;
-  static __device__ inline uint16_t cvt(float x, float* back) {
-    const _Float16 h = (_Float16)x;
-    *back = (float)h;
-    uint16_t u;
-    __builtin_memcpy(&u, &h, 2);
-    return u;
-  }
-  static __device__ inline f32x4 mfma(vec a, vec b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct SplitT<1> {
-  typedef bf16x8 vec;
-  static __device__ inline uint16_t cvt(float x, float* back) {
-    const __bf16 h = (__bf16)x;
-    *back = (float)h;
-    uint16_t u;
-    __builtin_memcpy(&u, &h, 2);
-    return u;
-  }
-  static __device__ inline f32x4 mfma(vec a, vec b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-};
-
-template <int TM, int NTW, int BF16, int AM, int CM, int BLDS>
-__global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Operand Bo,
-                                                               Operand Co, uint64_t s0,
-                                                               GemmGeom g) {
-  typedef SplitT<BF16> S;
-  typedef typename S::vec vec;
-  extern __shared__ __align__(16) uint16_t sBh[];
-  const int z = blockIdx.z;
-  const float* __restrict__ A = (const float*)op_base(Ao, z, s0);
-  const char* bblock = op_base(Bo, z, s0);
-  const float inv_b = *(const float*)bblock;
-  const uint16_t* __restrict__ Bh = (const uint16_t*)(bblock + kBranchHeader);
-  const size_t part = (size_t)g.KC * g.NT * 512;  // halves per part (hi or lo)
-  const uint16_t* __restrict__ Bl = Bh + part;
-  float* __restrict__ C = (float*)op_base(Co, z, s0);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int grp = lane >> 4;
-  const int r16 = lane & 15;
-  const int nt0 = blockIdx.y * NTW;
-  const int ntw = min(NTW, g.NT - nt0);
-  uint16_t* sBl = sBh + (size_t)g.KC * NTW * 512;
-
-  if (BLDS) {
-    const int per_kc = ntw * 512;  // halves of one part per k chunk
-    for (int i = threadIdx.x * 8; i < g.KC * per_kc; i += 2048) {
-      const int kc = i / per_kc, r = i - kc * per_kc;
-      const size_t src = (size_t)(kc * g.NT + nt0) * 512 + r;
-      *(u16x8*)(sBh + kc * NTW * 512 + r) = *(const u16x8*)(Bh + src);
-      *(u16x8*)(sBl + kc * NTW * 512 + r) = *(const u16x8*)(Bl + src);
-    }
-    __syncthreads();
-  }
-
-  const int64_t rows_per_wg = 4 * 16 * TM;
-  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
-    if (row0 >= g.M) continue;
-    f32x4 acc[TM][NTW];
-    int64_t rb[TM];
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      rb[t] = row < g.M ? row_base(row, g) : -1;
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int kc = 0; kc < g.KC; ++kc) {
-      const int kr0 = kc * 32 + grp * 8;
-      int64_t ko[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) ko[i] = k_offset((kr0 >> 1) + i, g);
-      vec ahi[TM], alo[TM];
-      float inv_a[TM];
-#pragma unroll
-      for (int t = 0; t < TM; ++t) {
-        const f32x4 x0 = load_kr4<AM>(A, rb[t], kr0, ko[0], ko[1], g);
-        const f32x4 x1 = load_kr4<AM>(A, rb[t], kr0 + 4, ko[2], ko[3], g);
-        const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-        float scale = 1.f;
-        inv_a[t] = 1.f;
-        if (!BF16) {
-          float mx = 0.f;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(x[i]));
-          mx = fmaxf(mx, __shfl_xor(mx, 16));
-          mx = fmaxf(mx, __shfl_xor(mx, 32));
-          if (mx > 0.f) {
-            int ex;
-            frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
-            scale = ldexpf(1.f, 14 - ex);
-            inv_a[t] = ldexpf(1.f, ex - 14);
-          }
-        }
-        u16x8 h, l;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float xs = x[i] * scale;
-          float back, dummy;
-          h[i] = S::cvt(xs, &back);
-          l[i] = S::cvt(xs - back, &dummy);
-        }
-        __builtin_memcpy(&ahi[t], &h, 16);
-        __builtin_memcpy(&alo[t], &l, 16);
-      }
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) {
-        if (n < ntw) {
-          u16x8 bh, bl;
-          if (BLDS) {
-            const size_t fo = ((size_t)(kc * NTW + n) * 64 + lane) * 8;
-            bh = *(const u16x8*)(sBh + fo);
-            bl = *(const u16x8*)(sBl + fo);
-          } else {
-            const size_t fo = ((size_t)(kc * g.NT + nt0 + n) * 64 + lane) * 8;
-            bh = *(const u16x8*)(Bh + fo);
-            bl = *(const u16x8*)(Bl + fo);
-          }
-          vec vbh, vbl;
-          __builtin_memcpy(&vbh, &bh, 16);
-          __builtin_memcpy(&vbl, &bl, 16);
-          f32x4 part3[TM];
-#pragma unroll
-          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, ahi[t], f32x4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbl, ahi[t], part3[t]);
-#pragma unroll
-          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, alo[t], part3[t]);
-#pragma unroll
-          for (int t = 0; t < TM; ++t) acc[t][n] += part3[t] * inv_a[t];
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      if (row >= g.M) continue;
-#pragma unroll
-      for (int n = 0; n < NTW; ++n)
-        if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n] * inv_b, g);
-    }
-  }
 }
 
 static uint16_t host_f16(float x, float* back) {
@@ -637,36 +160,6 @@ int build_bfrag_split(const float* b, int64_t K, int64_t N, int bf16, uint16_t* 
         }
   return eb;
 }
-
-template <int TM, int NTW, int BF16, int AM, int CM>
-static void launch_split_t(const LaunchCtx& c) {
-  const dim3 grid = gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks);
-  const size_t lds = (size_t)c.g.KC * NTW * 512 * 2 * 2;
-  if (lds <= (size_t)kLdsBudget && c.sch.lds != 0)
-    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1>), grid, dim3(256), lds,
-                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
-  else
-    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 0>), grid, dim3(256), 0,
-                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
-}
-
-template <int BF16, int AM, int CM>
-static void launch_split_n(const LaunchCtx& c) {
-  STEM_TM_NTW_DISPATCH(launch_split_t, BF16, AM, CM)
-}
-
-template <int BF16>
-static void launch_split_b(const LaunchCtx& c, const GemmLayout& lay) {
-  if (lay.amode == 0 && lay.cmode == 0)
-    launch_split_n<BF16, 0, 0>(c);
-  else if (lay.amode == 0)
-    launch_split_n<BF16, 0, 1>(c);
-  else if (lay.cmode == 0)
-    launch_split_n<BF16, 1, 0>(c);
-  else
-    launch_split_n<BF16, 1, 1>(c);
-}
-
 hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const Operand& C,
                         uint64_t s0, int nz, int64_t M, int64_t K, int64_t N,
                         const GemmLayout& lay, const GemmSched& sched, hipStream_t st) {
@@ -677,25 +170,12 @@ hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const
   c.s0 = s0;
   c.nz = nz;
   c.st = st;
-  if (precision == STEM_FP32) {
-    c.g = make_geom(lay, M, K, N, 16);
-    c.sch = resolve_sched(c.g, sched);
-    if (lay.amode == 0 && lay.cmode == 0)
-      launch_f32_m<0, 0>(c);
-    else if (lay.amode == 0)
-      launch_f32_m<0, 1>(c);
-    else if (lay.cmode == 0)
-      launch_f32_m<1, 0>(c);
-    else
-      launch_f32_m<1, 1>(c);
-  } else {
-    c.g = make_geom(lay, M, K, N, 32);
-    c.sch = resolve_sched(c.g, sched);
-    if (precision == STEM_SPLIT_BF16)
-      launch_split_b<1>(c, lay);
-    else
-      launch_split_b<0>(c, lay);
-  }
+  c.g = make_geom(lay, M, K, N, precision == STEM_FP32 ? 16 : 32);
+  c.sch = resolve_sched(c.g, sched);
+  if (precision == STEM_FP32)
+    launch_gemm_f32(c, lay);
+  else
+    launch_gemm_split(c, lay, precision == STEM_SPLIT_BF16);
   return hipGetLastError();
 }
 

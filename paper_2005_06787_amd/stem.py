@@ -187,10 +187,23 @@ class Plan:
             flags, _stream_handle(stream)))
         return out
 
+    def tune(self, slices_in_flight: int | None = None, reps: int = 3,
+             cache_path: str | None = None, stream=None) -> list[dict]:
+        """Autotune every step's product schedule (C-ABI stem_tune) at the
+        given slices per launch; returns the step infos after tuning."""
+        if slices_in_flight is None:
+            slices_in_flight = self.default_slices_in_flight(1 << self.n_sliced)
+        ws = self.workspace(slices_in_flight)
+        path = cache_path.encode() if cache_path else None
+        C.check(C.lib().stem_tune(self._h, int(slices_in_flight), ctypes.c_void_p(ws.data_ptr()),
+                                  ws.numel(), int(reps), path, _stream_handle(stream)))
+        return self.steps()
+
     def close(self):
         if getattr(self, "_h", None):
             C.lib().stem_plan_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
