@@ -228,8 +228,21 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default launch schedules")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the isolated-stem and batched-circuit workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy and exit (counter calibration)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache / measurement log")
     args = ap.parse_args()
+    if args.copy_calibration:
+        # one plain device-to-device copy of 1 GiB, to calibrate the HBM
+        # traffic counters (FETCH_SIZE / WRITE_SIZE) against a known size
+        import torch
+
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "layout is a design, not a measured path", file=sys.stderr)
