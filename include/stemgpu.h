@@ -298,6 +298,20 @@ stem_status stem_mlp_predict(stem_mlp_t mlp, const float* x, int32_t n, float* y
 stem_status stem_mlp_destroy(stem_mlp_t mlp);
 
 /*
+ * Ceiling microbenchmarks (asynchronous on `stream`; time them with events).
+ * stem_mb_copy: grid-stride copy of `bytes` from src to dst (device), one
+ *   vec_bytes (8 or 16) access per lane per iteration, `blocks` workgroups
+ *   of 256 threads.
+ * stem_mb_mfma: `blocks` workgroups of 256 threads; every wave issues
+ *   8 x iters independent MFMAs of one kind: 0 = f32 16x16x4 (2048 flops),
+ *   1 = f16 16x16x32, 2 = bf16 16x16x32 (16384 flops each); out (device,
+ *   blocks * 256 floats) receives a checksum so nothing is folded away.
+ */
+stem_status stem_mb_copy(const void* src, void* dst, uint64_t bytes, int32_t vec_bytes,
+                         int32_t blocks, void* stream);
+stem_status stem_mb_mfma(int32_t kind, int64_t iters, int32_t blocks, float* out, void* stream);
+
+/*
  * Fill dst (device, n complex64) with the counter-based test tensor: entry i
  * takes SplitMix64 outputs 4i..4i+3 of stream `seed` (Steele, Lea and Flood,
  * OOPSLA 2014); each 64-bit output gives two 22-bit integers (bits 42-63 and

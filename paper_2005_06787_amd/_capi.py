@@ -109,6 +109,10 @@ SIGNATURES = {
     "stem_mlp_predict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "stem_mlp_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "stem_mb_copy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "stem_mb_mfma": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "stem_plan_validate": (ctypes.c_int32, [ctypes.POINTER(stem_plan_desc),
                                             ctypes.POINTER(stem_plan_summary)]),
     "stem_plan_create": (ctypes.c_int32, [ctypes.POINTER(stem_plan_desc), ctypes.c_void_p,

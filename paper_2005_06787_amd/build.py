@@ -18,7 +18,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libstemgpu.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["gemm_f32.hip", "gemm_split.hip", "kernels.hip", "api.hip", "mlp.hip", "plan.cpp",
+SOURCES = ["gemm_f32.hip", "gemm_split.hip", "kernels.hip", "api.hip", "mlp.hip", "microbench.hip", "plan.cpp",
            "cost.cpp"]
 
 # Packed FP32 instructions are kept out of every kernel: only scalar FP32

@@ -52,11 +52,20 @@ __device__ __forceinline__ const char* op_base(const Operand& o, int z, uint64_t
 // 4 labels sit at the bottom without a separate permute pass.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int64_t row_base(int64_t m, const GemmGeom& g) {
+// The row start splits into a per-lane part (m & 15 = the lane's row in its
+// 16-row block, fixed for the whole kernel) and a wave-uniform part
+// (m >> 4, the block), so the expensive bit spreading of the block index
+// runs on the scalar unit; likewise a k offset splits into the lane's low
+// k bits and the chunk's uniform high bits (kpos of disjoint bit sets ORs).
+__device__ __forceinline__ int64_t row_lo(int r16, const GemmGeom& g) {
   int64_t lo = 0;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) lo |= ((m >> b) & 1ll) << g.mlo[b];
-  int64_t a = m >> 4;
+  for (int b = 0; b < 4; ++b) lo |= (int64_t)((r16 >> b) & 1) << g.mlo[b];
+  return lo;
+}
+
+__device__ __forceinline__ int64_t row_hi(int64_t mh, const GemmGeom& g) {
+  int64_t a = mh;
 #pragma unroll
   for (int i = 0; i < kMaxShared + 4; ++i) {
     if (i < g.nins) {
@@ -64,7 +73,7 @@ __device__ __forceinline__ int64_t row_base(int64_t m, const GemmGeom& g) {
       a = ((a >> p) << (p + 1)) | (a & ((1ll << p) - 1));
     }
   }
-  return a | lo;
+  return a;
 }
 
 __device__ __forceinline__ int64_t k_offset(int k, const GemmGeom& g) {
@@ -73,6 +82,11 @@ __device__ __forceinline__ int64_t k_offset(int k, const GemmGeom& g) {
   for (int i = 0; i < kMaxShared; ++i)
     if (i < g.s) a |= (int64_t)((k >> i) & 1) << g.spos[i];
   return a;
+}
+
+// Index of the calling wave in its workgroup, as a scalar.
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
 
 // 4 consecutive reals A[m][kr0 .. kr0+3] (= complex k0 = kr0/2 and k0+1);

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
   const float* __restrict__ Bf = (const float*)(op_base(Bo, z, s0) + kBranchHeader);
   float* __restrict__ C = (float*)op_base(Co, z, s0);
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_id();
   const int grp = lane >> 4;
   const int r16 = lane & 15;
   const int nt0 = blockIdx.y * NTW;
@@ -45,6 +45,11 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
     __syncthreads();
   }
 
+  // lane constants: row bits 0..3 and k bits 0..2 (k = 8 kc + 2 grp + i)
+  const int64_t rlo = row_lo(r16, g);
+  const int64_t kl0 = k_offset(2 * grp, g);
+  const int64_t kl1 = k_offset(2 * grp + 1, g);
+
   const int64_t rows_per_wg = 4 * 16 * TM;
   const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -54,47 +59,47 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
     int64_t rb[TM];
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      rb[t] = row < g.M ? row_base(row, g) : -1;
+      const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
+      rb[t] = row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
 #pragma unroll
       for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     f32x4 a[TM];
-    {
-      const int kr0 = grp * 4;
-      const int64_t ko0 = k_offset(kr0 >> 1, g);
-      const int64_t ko1 = AM == 1 ? k_offset((kr0 >> 1) + 1, g) : 0;
 #pragma unroll
-      for (int t = 0; t < TM; ++t) a[t] = load_kr4<AM>(A, rb[t], kr0, ko0, ko1, g);
-    }
+    for (int t = 0; t < TM; ++t) a[t] = load_kr4<AM>(A, rb[t], grp * 4, kl0, kl1, g);
     for (int kc = 0; kc < g.KC; ++kc) {
       // prefetch the next k chunk of A while this one is multiplied
       f32x4 an[TM];
       if (kc + 1 < g.KC) {
-        const int kr1 = (kc + 1) * 16 + grp * 4;
-        const int64_t ko0 = k_offset(kr1 >> 1, g);
-        const int64_t ko1 = AM == 1 ? k_offset((kr1 >> 1) + 1, g) : 0;
+        const int64_t kh = k_offset(8 * (kc + 1), g);  // wave-uniform
 #pragma unroll
-        for (int t = 0; t < TM; ++t) an[t] = load_kr4<AM>(A, rb[t], kr1, ko0, ko1, g);
+        for (int t = 0; t < TM; ++t)
+          an[t] = load_kr4<AM>(A, rb[t], (kc + 1) * 16 + grp * 4, kh | kl0, kh | kl1, g);
       }
+      // all branch fragments of this k chunk first, then the MFMAs ordered
+      // so that TM * NTW independent accumulators separate two dependent
+      // ones
+      float b[NTW][4];
 #pragma unroll
       for (int n = 0; n < NTW; ++n) {
         if (n < ntw) {
-          float b[4];
-          if (BLDS) {
-            const float* bp = sB + (kc * NTW + n) * 256 + lane;
-            b[0] = bp[0]; b[1] = bp[64]; b[2] = bp[128]; b[3] = bp[192];
-          } else {
-            const float* bp = Bf + ((size_t)(kc * g.NT + nt0 + n) * 4) * 64 + lane;
-            b[0] = bp[0]; b[1] = bp[64]; b[2] = bp[128]; b[3] = bp[192];
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int t = 0; t < TM; ++t)
-              acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[t][j], acc[t][n], 0, 0, 0);
+          const float* bp = BLDS ? sB + (kc * NTW + n) * 256 + lane
+                                 : Bf + ((size_t)(kc * g.NT + nt0 + n) * 4) * 64 + lane;
+          b[n][0] = bp[0];
+          b[n][1] = bp[64];
+          b[n][2] = bp[128];
+          b[n][3] = bp[192];
         }
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int n = 0; n < NTW; ++n)
+          if (n < ntw) {
+#pragma unroll
+            for (int t = 0; t < TM; ++t)
+              acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[n][j], a[t][j], acc[t][n], 0, 0, 0);
+          }
       if (kc + 1 < g.KC) {
 #pragma unroll
         for (int t = 0; t < TM; ++t) a[t] = an[t];

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
   const uint16_t* __restrict__ Bl = Bh + part;
   float* __restrict__ C = (float*)op_base(Co, z, s0);
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_id();
   const int grp = lane >> 4;
   const int r16 = lane & 15;
   const int nt0 = blockIdx.y * NTW;
@@ -84,6 +84,12 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
     __syncthreads();
   }
 
+  // lane constants: row bits 0..3 and k bits 0..3 (k = 16 kc + 4 grp + i)
+  const int64_t rlo = row_lo(r16, g);
+  int64_t kl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) kl[i] = k_offset(4 * grp + i, g);
+
   const int64_t rows_per_wg = 4 * 16 * TM;
   const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -93,16 +99,17 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
     int64_t rb[TM];
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      rb[t] = row < g.M ? row_base(row, g) : -1;
+      const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
+      rb[t] = row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
 #pragma unroll
       for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     for (int kc = 0; kc < g.KC; ++kc) {
       const int kr0 = kc * 32 + grp * 8;
+      const int64_t kh = k_offset(16 * kc, g);  // wave-uniform
       int64_t ko[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ko[i] = k_offset((kr0 >> 1) + i, g);
+      for (int i = 0; i < 4; ++i) ko[i] = kh | kl[i];
       vec ahi[TM], alo[TM];
       float inv_a[TM];
 #pragma unroll
@@ -152,15 +159,26 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
           vec vbh, vbl;
           __builtin_memcpy(&vbh, &bh, 16);
           __builtin_memcpy(&vbl, &bl, 16);
-          f32x4 part3[TM];
+          if (BF16) {
+            // no scale: the three products accumulate in place
 #pragma unroll
-          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, ahi[t], f32x4{0.f, 0.f, 0.f, 0.f});
+            for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbh, ahi[t], acc[t][n]);
 #pragma unroll
-          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbl, ahi[t], part3[t]);
+            for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbl, ahi[t], acc[t][n]);
 #pragma unroll
-          for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, alo[t], part3[t]);
+            for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbh, alo[t], acc[t][n]);
+          } else {
+            f32x4 part3[TM];
 #pragma unroll
-          for (int t = 0; t < TM; ++t) acc[t][n] += part3[t] * inv_a[t];
+            for (int t = 0; t < TM; ++t)
+              part3[t] = S::mfma(vbh, ahi[t], f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbl, ahi[t], part3[t]);
+#pragma unroll
+            for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, alo[t], part3[t]);
+#pragma unroll
+            for (int t = 0; t < TM; ++t) acc[t][n] += part3[t] * inv_a[t];
+          }
         }
       }
     }
