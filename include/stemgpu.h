@@ -301,7 +301,8 @@ stem_status stem_mlp_destroy(stem_mlp_t mlp);
  * Ceiling microbenchmarks (asynchronous on `stream`; time them with events).
  * stem_mb_copy: grid-stride copy of `bytes` from src to dst (device), one
  *   vec_bytes (8 or 16) access per lane per iteration, `blocks` workgroups
- *   of 256 threads.
+ *   of 256 threads; vec_bytes 64 = four 16-byte loads in flight per lane,
+ *   65 = the same with non-temporal loads and stores.
  * stem_mb_mfma: `blocks` workgroups of 256 threads; every wave issues
  *   8 x iters independent MFMAs of one kind: 0 = f32 16x16x4 (2048 flops),
  *   1 = f16 16x16x32, 2 = bf16 16x16x32 (16384 flops each); out (device,

@@ -90,33 +90,59 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
 #pragma unroll
   for (int i = 0; i < 4; ++i) kl[i] = k_offset(4 * grp + i, g);
 
+  // The wave's row blocks are blk = blockIdx.x, + gridDim.x, ...; the raw
+  // A values of the chunk after the current one are always in flight, also
+  // across the boundary from one row block to the next.
   const int64_t rows_per_wg = 4 * 16 * TM;
   const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
-    if (row0 >= g.M) continue;
-    f32x4 acc[TM][NTW];
-    int64_t rb[TM];
+  int64_t blk = blockIdx.x;
+  if ((blk * 4 + wave) * (16 * TM) >= g.M) return;  // no barrier follows
+  int64_t rb[TM];
+  f32x4 x0[TM], x1[TM];
 #pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
-      rb[t] = row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
+  for (int t = 0; t < TM; ++t) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
+    rb[t] = row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
+    x0[t] = load_kr4<AM>(A, rb[t], grp * 8, kl[0], kl[1], g);
+    x1[t] = load_kr4<AM>(A, rb[t], grp * 8 + 4, kl[2], kl[3], g);
+  }
+  while (true) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t nxt = blk + gridDim.x;
+    const int64_t row0n = (nxt * 4 + wave) * (16 * TM);
+    const bool has_next = nxt < nblk && row0n < g.M;
+    f32x4 acc[TM][NTW];
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
 #pragma unroll
       for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    int64_t rbn[TM];
     for (int kc = 0; kc < g.KC; ++kc) {
-      const int kr0 = kc * 32 + grp * 8;
-      const int64_t kh = k_offset(16 * kc, g);  // wave-uniform
-      int64_t ko[4];
+      f32x4 y0[TM], y1[TM];
+      if (kc + 1 < g.KC) {
+        const int kr0 = (kc + 1) * 32 + grp * 8;
+        const int64_t kh = k_offset(16 * (kc + 1), g);  // wave-uniform
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ko[i] = kh | kl[i];
+        for (int t = 0; t < TM; ++t) {
+          y0[t] = load_kr4<AM>(A, rb[t], kr0, kh | kl[0], kh | kl[1], g);
+          y1[t] = load_kr4<AM>(A, rb[t], kr0 + 4, kh | kl[2], kh | kl[3], g);
+        }
+      } else if (has_next) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          const int64_t hi = row_hi((row0n >> 4) + t, g);
+          rbn[t] = row0n + t * 16 + r16 < g.M ? (hi | rlo) : -1;
+          y0[t] = load_kr4<AM>(A, rbn[t], grp * 8, kl[0], kl[1], g);
+          y1[t] = load_kr4<AM>(A, rbn[t], grp * 8 + 4, kl[2], kl[3], g);
+        }
+      }
       vec ahi[TM], alo[TM];
       float inv_a[TM];
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        const f32x4 x0 = load_kr4<AM>(A, rb[t], kr0, ko[0], ko[1], g);
-        const f32x4 x1 = load_kr4<AM>(A, rb[t], kr0 + 4, ko[2], ko[3], g);
-        const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        const float x[8] = {x0[t].x, x0[t].y, x0[t].z, x0[t].w,
+                            x1[t].x, x1[t].y, x1[t].z, x1[t].w};
         float scale = 1.f;
         inv_a[t] = 1.f;
         if (!BF16) {
@@ -181,6 +207,13 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
           }
         }
       }
+      if (kc + 1 < g.KC || has_next) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          x0[t] = y0[t];
+          x1[t] = y1[t];
+        }
+      }
     }
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
@@ -190,6 +223,10 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
       for (int n = 0; n < NTW; ++n)
         if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n] * inv_b, g);
     }
+    if (!has_next) break;
+    blk = nxt;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) rb[t] = rbn[t];
   }
 }
 

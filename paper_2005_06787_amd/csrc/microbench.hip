@@ -24,6 +24,30 @@ __global__ __launch_bounds__(256) void mb_copy_kernel(const T* __restrict__ src,
     dst[i] = src[i];
 }
 
+// UNROLL loads in flight per lane before the stores; NT: non-temporal
+// (streaming) loads and stores.
+template <int UNROLL, int NT>
+__global__ __launch_bounds__(256) void mb_copy_unrolled_kernel(const f32x4* __restrict__ src,
+                                                               f32x4* __restrict__ dst,
+                                                               uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (UNROLL - 1) * stride < n; i += UNROLL * stride) {
+    f32x4 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u)
+      v[u] = NT ? __builtin_nontemporal_load(src + i + u * stride) : src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      if (NT)
+        __builtin_nontemporal_store(v[u], dst + i + u * stride);
+      else
+        dst[i + u * stride] = v[u];
+    }
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
 // Every wave runs 8 independent accumulator chains of `iters` MFMAs each;
 // the operands are lane values that the compiler cannot fold.
 template <int KIND>
@@ -79,12 +103,19 @@ stem_status stem_mb_copy(const void* src, void* dst, uint64_t bytes, int32_t vec
     set_error("null pointer");
     return STEM_EINVAL;
   }
-  if ((vec_bytes != 8 && vec_bytes != 16) || bytes % (uint64_t)vec_bytes || blocks < 1) {
-    set_error("vec_bytes must be 8 or 16 and divide bytes; blocks >= 1");
+  const bool unrolled = vec_bytes == 64 || vec_bytes == 65;
+  if ((vec_bytes != 8 && vec_bytes != 16 && !unrolled) || bytes % 16 || blocks < 1) {
+    set_error("vec_bytes must be 8, 16, 64 or 65 and bytes a multiple of 16; blocks >= 1");
     return STEM_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
-  if (vec_bytes == 16)
+  if (vec_bytes == 64)
+    hipLaunchKernelGGL((mb_copy_unrolled_kernel<4, 0>), dim3(blocks), dim3(256), 0, st,
+                       (const f32x4*)src, (f32x4*)dst, bytes / 16);
+  else if (vec_bytes == 65)
+    hipLaunchKernelGGL((mb_copy_unrolled_kernel<4, 1>), dim3(blocks), dim3(256), 0, st,
+                       (const f32x4*)src, (f32x4*)dst, bytes / 16);
+  else if (vec_bytes == 16)
     hipLaunchKernelGGL(mb_copy_kernel<f32x4>, dim3(blocks), dim3(256), 0, st, (const f32x4*)src,
                        (f32x4*)dst, bytes / 16);
   else
