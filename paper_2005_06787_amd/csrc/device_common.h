@@ -91,10 +91,17 @@ __device__ __forceinline__ int wave_id() {
 
 // 4 consecutive reals A[m][kr0 .. kr0+3] (= complex k0 = kr0/2 and k0+1);
 // ko0/ko1 are the offsets of those two k values (adjacent in K-low mode).
-template <int AM>
+// FULL: the caller guarantees a valid row (rb >= 0) and kr0 + 4 <= 2K.
+template <int AM, int FULL>
 __device__ __forceinline__ f32x4 load_kr4(const float* __restrict__ A, int64_t rb, int kr0,
                                           int64_t ko0, int64_t ko1, const GemmGeom& g) {
   f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (FULL) {
+    if (AM == 0) return *(const f32x4*)(A + 2 * (rb + ko0));
+    const float2 t0 = *(const float2*)(A + 2 * (rb + ko0));
+    const float2 t1 = *(const float2*)(A + 2 * (rb + ko1));
+    return f32x4{t0.x, t0.y, t1.x, t1.y};
+  }
   if (rb < 0) return v;
   if (AM == 0) {
     if (kr0 < g.Kr) {
@@ -123,23 +130,30 @@ __device__ __forceinline__ f32x4 load_kr4(const float* __restrict__ A, int64_t r
   return v;
 }
 
-// Store the 4 consecutive reals C[m][nr0 .. nr0+3].
-template <int CM>
+// Store the 4 consecutive reals C[m][nr0 .. nr0+3]; FULL: nr0 + 4 <= 2N.
+template <int CM, int FULL>
 __device__ __forceinline__ void store_nr4(float* __restrict__ C, int64_t m, int nr0, f32x4 v,
                                           const GemmGeom& g) {
   if (CM == 0) {
-    if (nr0 >= g.Nr) return;
+    if (!FULL && nr0 >= g.Nr) return;
     float* dst = C + m * (int64_t)g.Nr + nr0;
-    if (g.Nr >= 4)
+    if (FULL || g.Nr >= 4)
       *(f32x4*)dst = v;
     else
       *(float2*)dst = float2{v.x, v.y};
   } else {
     const int n0 = nr0 >> 1;
     const int64_t base = ((m >> 4) << (4 + g.f)) | (m & 15);
-    if (n0 < g.N) *(float2*)(C + 2 * (base | ((int64_t)n0 << 4))) = float2{v.x, v.y};
-    if (n0 + 1 < g.N) *(float2*)(C + 2 * (base | ((int64_t)(n0 + 1) << 4))) = float2{v.z, v.w};
+    if (FULL || n0 < g.N) *(float2*)(C + 2 * (base | ((int64_t)n0 << 4))) = float2{v.x, v.y};
+    if (FULL || n0 + 1 < g.N)
+      *(float2*)(C + 2 * (base | ((int64_t)(n0 + 1) << 4))) = float2{v.z, v.w};
   }
+}
+
+// The next value of a bit-spread counter: positions `mask` hold the
+// counter's bits, all other positions are ignored.
+__device__ __forceinline__ int64_t spread_next(int64_t x, int64_t mask) {
+  return ((x | ~mask) + 1) & mask;
 }
 
 static inline GemmGeom make_geom(const GemmLayout& lay, int64_t M, int64_t K, int64_t N, int kq) {
@@ -167,7 +181,9 @@ static inline GemmSched resolve_sched(const GemmGeom& g, GemmSched s) {
   while (nt2 < g.NT) nt2 <<= 1;
   if (s.ntw <= 0) s.ntw = std::min(8, nt2);
   s.ntw = std::min(s.ntw, std::min(8, nt2));
+  while (s.ntw & (s.ntw - 1)) s.ntw &= s.ntw - 1;  // a power of two: NT % ntw == 0
   if (s.tm <= 0) s.tm = s.ntw <= 2 ? 4 : 2;
+  s.tm = s.tm >= 4 ? 4 : s.tm >= 2 ? 2 : 1;
   if (s.blocks <= 0) s.blocks = kTargetBlocks;
   return s;
 }
@@ -181,6 +197,15 @@ static inline dim3 gemm_grid(const GemmGeom& g, int TM, int NTW, int nz, int tar
   const int64_t want = std::max<int64_t>(1, target / ((int64_t)gy * nz));
   const int64_t gx = std::min<int64_t>(nblk, want);
   return dim3((unsigned)gx, (unsigned)gy, (unsigned)nz);
+}
+
+// True when every row block, k chunk and column tile of the launch is
+// whole, so the kernel runs without bounds predicates: M a multiple of the
+// rows per workgroup, 2K of the k chunk (kq reals), 2N of the tile width,
+// output in block order (CM = 1).
+static inline bool gemm_full(const GemmGeom& g, int TM, int NTW, int CM, int kq) {
+  return CM == 1 && g.M % (64 * TM) == 0 && g.Kr % kq == 0 && g.Nr % 16 == 0 &&
+         g.NT % NTW == 0;
 }
 
 struct LaunchCtx {

@@ -20,8 +20,123 @@ namespace stem {
 // times) and NTW 16-column tiles; blockIdx.y splits wide outputs.  With
 // BLDS the workgroup first copies its branch fragments into LDS; the
 // workgroups then loop over the row blocks.
+//
+// A streams through a ring of R register buffers, one k chunk each, in one
+// flat sequence over the wave's row blocks: right after the MFMAs of a
+// chunk, its buffer is refilled with the chunk R places later (in the next
+// row block once the current one runs out), so R - 1 chunks are always in
+// flight.  The refill is issued unconditionally (the last row block
+// re-reads its own rows) so that every path issues the loads in the same
+// order and the memory-counter waits stay exact.
 // ---------------------------------------------------------------------------
-template <int TM, int NTW, int AM, int CM, int BLDS>
+template <int R, int TM, int NTW, int AM, int CM, int BLDS, int FULL>
+__device__ __forceinline__ void f32_rows(const float* __restrict__ A,
+                                         const float* __restrict__ Bsrc, float* __restrict__ C,
+                                         const GemmGeom& g, int wave, int lane, int nt0, int ntw) {
+  const int grp = lane >> 4;
+  const int r16 = lane & 15;
+  // lane constants: row bits 0..3 and k bits 0..2 (k = 8 kc + 2 grp + i);
+  // the chunk's k bits 3.. advance as a bit-spread counter over khmask,
+  // which wraps to chunk 0 after the last one
+  const int64_t rlo = row_lo(r16, g);
+  const int64_t kl0 = k_offset(2 * grp, g);
+  const int64_t kl1 = k_offset(2 * grp + 1, g);
+  const int64_t khmask = k_offset(g.K - 1, g) & ~k_offset(7, g);
+  const int64_t rows_per_wg = 4 * 16 * TM;
+  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
+
+  auto block_rows = [&](int64_t blk, int64_t (&rb)[TM]) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
+      rb[t] = FULL || row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
+    }
+  };
+  auto load_chunk = [&](f32x4 (&dst)[TM], const int64_t (&rb)[TM], int kc, int64_t kh) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+      dst[t] = load_kr4<AM, FULL>(A, rb[t], kc * 16 + grp * 4, kh | kl0, kh | kl1, g);
+  };
+
+  int64_t blk = blockIdx.x;
+  if ((blk * 4 + wave) * (16 * TM) >= g.M) return;  // no barrier follows
+  int64_t rb[TM];
+  block_rows(blk, rb);
+  f32x4 buf[R][TM];
+  int64_t kh = 0;  // k offset of the chunk loaded last
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (i > 0) kh = spread_next(kh, khmask);
+    load_chunk(buf[i], rb, i, kh);
+  }
+  while (true) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t nxt = blk + gridDim.x;
+    const bool has_next = nxt < nblk && (FULL || (nxt * 4 + wave) * (16 * TM) < g.M);
+    int64_t rbn[TM];
+    if (has_next)
+      block_rows(nxt, rbn);
+    else
+#pragma unroll
+      for (int t = 0; t < TM; ++t) rbn[t] = rb[t];
+    f32x4 acc[TM][NTW];
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < g.KC; kc += R) {
+      const bool tail = kc + R >= g.KC;  // refills come from the next row block
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        // all branch fragments of the chunk first, then the MFMAs ordered so
+        // that TM * NTW independent accumulators separate two dependent ones
+        float b[NTW][4];
+#pragma unroll
+        for (int n = 0; n < NTW; ++n) {
+          if (n < ntw) {
+            const float* bp = BLDS ? Bsrc + ((kc + i) * NTW + n) * 256 + lane
+                                   : Bsrc + ((size_t)((kc + i) * g.NT + nt0 + n) * 4) * 64 + lane;
+            b[n][0] = bp[0];
+            b[n][1] = bp[64];
+            b[n][2] = bp[128];
+            b[n][3] = bp[192];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int n = 0; n < NTW; ++n)
+            if (n < ntw) {
+#pragma unroll
+              for (int t = 0; t < TM; ++t)
+                acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[n][j], buf[i][t][j], acc[t][n],
+                                                                 0, 0, 0);
+            }
+        kh = spread_next(kh, khmask);
+        int64_t rl[TM];
+#pragma unroll
+        for (int t = 0; t < TM; ++t) rl[t] = tail ? rbn[t] : rb[t];
+        load_chunk(buf[i], rl, (kc + i + R) & (g.KC - 1), kh);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t row = row0 + t * 16 + r16;
+      if (!FULL && row >= g.M) continue;
+#pragma unroll
+      for (int n = 0; n < NTW; ++n)
+        if (n < ntw) store_nr4<CM, FULL>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n], g);
+    }
+    if (!has_next) break;
+    blk = nxt;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) rb[t] = rbn[t];
+  }
+}
+
+template <int TM, int NTW, int AM, int CM, int BLDS, int FULL>
 __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand Bo, Operand Co,
                                                              uint64_t s0, GemmGeom g) {
   extern __shared__ __align__(16) float sB[];
@@ -31,10 +146,9 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
   float* __restrict__ C = (float*)op_base(Co, z, s0);
   const int lane = threadIdx.x & 63;
   const int wave = wave_id();
-  const int grp = lane >> 4;
-  const int r16 = lane & 15;
   const int nt0 = blockIdx.y * NTW;
-  const int ntw = min(NTW, g.NT - nt0);
+  // FULL: every tile of the launch is whole (gemm_full), no predicates
+  const int ntw = FULL ? NTW : min(NTW, g.NT - nt0);
 
   if (BLDS) {
     const int per_kc = ntw * 256;
@@ -44,88 +158,44 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
     }
     __syncthreads();
   }
-
-  // lane constants: row bits 0..3 and k bits 0..2 (k = 8 kc + 2 grp + i)
-  const int64_t rlo = row_lo(r16, g);
-  const int64_t kl0 = k_offset(2 * grp, g);
-  const int64_t kl1 = k_offset(2 * grp + 1, g);
-
-  const int64_t rows_per_wg = 4 * 16 * TM;
-  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
-    if (row0 >= g.M) continue;
-    f32x4 acc[TM][NTW];
-    int64_t rb[TM];
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
-      rb[t] = row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    f32x4 a[TM];
-#pragma unroll
-    for (int t = 0; t < TM; ++t) a[t] = load_kr4<AM>(A, rb[t], grp * 4, kl0, kl1, g);
-    for (int kc = 0; kc < g.KC; ++kc) {
-      // prefetch the next k chunk of A while this one is multiplied
-      f32x4 an[TM];
-      if (kc + 1 < g.KC) {
-        const int64_t kh = k_offset(8 * (kc + 1), g);  // wave-uniform
-#pragma unroll
-        for (int t = 0; t < TM; ++t)
-          an[t] = load_kr4<AM>(A, rb[t], (kc + 1) * 16 + grp * 4, kh | kl0, kh | kl1, g);
-      }
-      // all branch fragments of this k chunk first, then the MFMAs ordered
-      // so that TM * NTW independent accumulators separate two dependent
-      // ones
-      float b[NTW][4];
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) {
-        if (n < ntw) {
-          const float* bp = BLDS ? sB + (kc * NTW + n) * 256 + lane
-                                 : Bf + ((size_t)(kc * g.NT + nt0 + n) * 4) * 64 + lane;
-          b[n][0] = bp[0];
-          b[n][1] = bp[64];
-          b[n][2] = bp[128];
-          b[n][3] = bp[192];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int n = 0; n < NTW; ++n)
-          if (n < ntw) {
-#pragma unroll
-            for (int t = 0; t < TM; ++t)
-              acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[n][j], a[t][j], acc[t][n], 0, 0, 0);
-          }
-      if (kc + 1 < g.KC) {
-#pragma unroll
-        for (int t = 0; t < TM; ++t) a[t] = an[t];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      if (row >= g.M) continue;
-#pragma unroll
-      for (int n = 0; n < NTW; ++n)
-        if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n], g);
-    }
+  const float* Bsrc = BLDS ? (const float*)sB : Bf;
+  // KC is a power of two; the ring holds min(4, KC) chunks (one for the
+  // small partial shapes that run without FULL)
+  if constexpr (FULL) {
+    if (g.KC >= 4)
+      f32_rows<4, TM, NTW, AM, CM, BLDS, FULL>(A, Bsrc, C, g, wave, lane, nt0, ntw);
+    else if (g.KC == 2)
+      f32_rows<2, TM, NTW, AM, CM, BLDS, FULL>(A, Bsrc, C, g, wave, lane, nt0, ntw);
+    else
+      f32_rows<1, TM, NTW, AM, CM, BLDS, FULL>(A, Bsrc, C, g, wave, lane, nt0, ntw);
+  } else {
+    f32_rows<1, TM, NTW, AM, CM, BLDS, FULL>(A, Bsrc, C, g, wave, lane, nt0, ntw);
   }
 }
 
-template <int TM, int NTW, int AM, int CM>
-static void launch_f32_t(const LaunchCtx& c) {
-  const dim3 grid = gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks);
+template <int TM, int NTW, int AM, int CM, int FULL>
+static void launch_f32_f(const LaunchCtx& c, const dim3& grid) {
   const size_t lds = (size_t)c.g.KC * NTW * 256 * 4;
   if (lds <= (size_t)kLdsBudget && c.sch.lds != 0)
-    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1>), grid, dim3(256), lds, c.st,
-                       *c.A, *c.B, *c.C, c.s0, c.g);
+    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1, FULL>), grid, dim3(256), lds,
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else
-    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 0>), grid, dim3(256), 0, c.st,
-                       *c.A, *c.B, *c.C, c.s0, c.g);
+    hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 0, FULL>), grid, dim3(256), 0,
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+}
+
+// Whole shapes run the requested schedule without predicates; partial ones
+// (small M, K or N) run one generic predicated kernel with one row block
+// per wave.
+template <int TM, int NTW, int AM, int CM>
+static void launch_f32_t(const LaunchCtx& c) {
+  if constexpr (CM == 1) {
+    if (gemm_full(c.g, TM, NTW, CM, 16)) {
+      launch_f32_f<TM, NTW, AM, CM, 1>(c, gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks));
+      return;
+    }
+  }
+  launch_f32_f<1, NTW, AM, CM, 0>(c, gemm_grid(c.g, 1, NTW, c.nz, c.sch.blocks));
 }
 
 template <int AM, int CM>

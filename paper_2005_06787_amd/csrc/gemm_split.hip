@@ -50,12 +50,174 @@ struct SplitT<1> {
   }
 };
 
-template <int TM, int NTW, int BF16, int AM, int CM, int BLDS>
+// A streams through a ring of R register buffers of raw FP32 chunks, in one
+// flat sequence over the wave's row blocks, as in the FP32 kernel: after a
+// chunk's MFMAs its buffer is refilled with the chunk R places later (from
+// the next row block at the end of the current one; the last row block
+// re-reads its own rows), so R - 1 chunks are in flight.
+template <int R, int TM, int NTW, int BF16, int AM, int CM, int BLDS, int FULL>
+__device__ __forceinline__ void split_rows(const float* __restrict__ A,
+                                           const uint16_t* __restrict__ Bh,
+                                           const uint16_t* __restrict__ Bl, float inv_b,
+                                           float* __restrict__ C, const GemmGeom& g, int wave,
+                                           int lane, int nt0, int ntw) {
+  typedef SplitT<BF16> S;
+  typedef typename S::vec vec;
+  const int grp = lane >> 4;
+  const int r16 = lane & 15;
+  // lane constants: row bits 0..3 and k bits 0..3 (k = 16 kc + 4 grp + i);
+  // the chunk's k bits 4.. advance as a bit-spread counter over khmask
+  const int64_t rlo = row_lo(r16, g);
+  int64_t kl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) kl[i] = k_offset(4 * grp + i, g);
+  const int64_t khmask = k_offset(g.K - 1, g) & ~k_offset(15, g);
+  const int64_t rows_per_wg = 4 * 16 * TM;
+  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
+
+  auto block_rows = [&](int64_t blk, int64_t (&rb)[TM]) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
+      rb[t] = FULL || row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
+    }
+  };
+  auto load_chunk = [&](f32x4 (&dst)[TM][2], const int64_t (&rb)[TM], int kc, int64_t kh) {
+    const int kr0 = kc * 32 + grp * 8;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      dst[t][0] = load_kr4<AM, FULL>(A, rb[t], kr0, kh | kl[0], kh | kl[1], g);
+      dst[t][1] = load_kr4<AM, FULL>(A, rb[t], kr0 + 4, kh | kl[2], kh | kl[3], g);
+    }
+  };
+
+  int64_t blk = blockIdx.x;
+  if ((blk * 4 + wave) * (16 * TM) >= g.M) return;  // no barrier follows
+  int64_t rb[TM];
+  block_rows(blk, rb);
+  f32x4 buf[R][TM][2];
+  int64_t kh = 0;  // k offset of the chunk loaded last
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (i > 0) kh = spread_next(kh, khmask);
+    load_chunk(buf[i], rb, i, kh);
+  }
+  while (true) {
+    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t nxt = blk + gridDim.x;
+    const bool has_next = nxt < nblk && (FULL || (nxt * 4 + wave) * (16 * TM) < g.M);
+    int64_t rbn[TM];
+    if (has_next)
+      block_rows(nxt, rbn);
+    else
+#pragma unroll
+      for (int t = 0; t < TM; ++t) rbn[t] = rb[t];
+    f32x4 acc[TM][NTW];
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < g.KC; kc += R) {
+      const bool tail = kc + R >= g.KC;  // refills come from the next row block
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        vec ahi[TM], alo[TM];
+        float inv_a[TM];
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          const f32x4 x0 = buf[i][t][0], x1 = buf[i][t][1];
+          const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          float scale = 1.f;
+          inv_a[t] = 1.f;
+          if (!BF16) {
+            float mx = 0.f;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(x[e]));
+            mx = fmaxf(mx, __shfl_xor(mx, 16));
+            mx = fmaxf(mx, __shfl_xor(mx, 32));
+            if (mx > 0.f) {
+              int ex;
+              frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
+              scale = ldexpf(1.f, 14 - ex);
+              inv_a[t] = ldexpf(1.f, ex - 14);
+            }
+          }
+          u16x8 h, l;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float xs = x[e] * scale;
+            float back, dummy;
+            h[e] = S::cvt(xs, &back);
+            l[e] = S::cvt(xs - back, &dummy);
+          }
+          __builtin_memcpy(&ahi[t], &h, 16);
+          __builtin_memcpy(&alo[t], &l, 16);
+        }
+        // the raw chunk is converted: refill its buffer now
+        kh = spread_next(kh, khmask);
+        {
+          int64_t rl[TM];
+#pragma unroll
+          for (int t = 0; t < TM; ++t) rl[t] = tail ? rbn[t] : rb[t];
+          load_chunk(buf[i], rl, (kc + i + R) & (g.KC - 1), kh);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int n = 0; n < NTW; ++n) {
+          if (n < ntw) {
+            const size_t fo = BLDS ? ((size_t)((kc + i) * NTW + n) * 64 + lane) * 8
+                                   : ((size_t)((kc + i) * g.NT + nt0 + n) * 64 + lane) * 8;
+            const u16x8 bh = *(const u16x8*)(Bh + fo);
+            const u16x8 bl = *(const u16x8*)(Bl + fo);
+            vec vbh, vbl;
+            __builtin_memcpy(&vbh, &bh, 16);
+            __builtin_memcpy(&vbl, &bl, 16);
+            if (BF16) {
+              // no scale: the three products accumulate in place
+#pragma unroll
+              for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbh, ahi[t], acc[t][n]);
+#pragma unroll
+              for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbl, ahi[t], acc[t][n]);
+#pragma unroll
+              for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbh, alo[t], acc[t][n]);
+            } else {
+              f32x4 part3[TM];
+#pragma unroll
+              for (int t = 0; t < TM; ++t)
+                part3[t] = S::mfma(vbh, ahi[t], f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+              for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbl, ahi[t], part3[t]);
+#pragma unroll
+              for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, alo[t], part3[t]);
+#pragma unroll
+              for (int t = 0; t < TM; ++t) acc[t][n] += part3[t] * inv_a[t];
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t row = row0 + t * 16 + r16;
+      if (!FULL && row >= g.M) continue;
+#pragma unroll
+      for (int n = 0; n < NTW; ++n)
+        if (n < ntw)
+          store_nr4<CM, FULL>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n] * inv_b, g);
+    }
+    if (!has_next) break;
+    blk = nxt;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) rb[t] = rbn[t];
+  }
+}
+
+template <int TM, int NTW, int BF16, int AM, int CM, int BLDS, int FULL>
 __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Operand Bo,
                                                                Operand Co, uint64_t s0,
                                                                GemmGeom g) {
-  typedef SplitT<BF16> S;
-  typedef typename S::vec vec;
   extern __shared__ __align__(16) uint16_t sBh[];
   const int z = blockIdx.z;
   const float* __restrict__ A = (const float*)op_base(Ao, z, s0);
@@ -67,10 +229,9 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
   float* __restrict__ C = (float*)op_base(Co, z, s0);
   const int lane = threadIdx.x & 63;
   const int wave = wave_id();
-  const int grp = lane >> 4;
-  const int r16 = lane & 15;
   const int nt0 = blockIdx.y * NTW;
-  const int ntw = min(NTW, g.NT - nt0);
+  // FULL: every tile of the launch is whole (gemm_full), no predicates
+  const int ntw = FULL ? NTW : min(NTW, g.NT - nt0);
   uint16_t* sBl = sBh + (size_t)g.KC * NTW * 512;
 
   if (BLDS) {
@@ -83,163 +244,45 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
     }
     __syncthreads();
   }
-
-  // lane constants: row bits 0..3 and k bits 0..3 (k = 16 kc + 4 grp + i)
-  const int64_t rlo = row_lo(r16, g);
-  int64_t kl[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) kl[i] = k_offset(4 * grp + i, g);
-
-  // The wave's row blocks are blk = blockIdx.x, + gridDim.x, ...; the raw
-  // A values of the chunk after the current one are always in flight, also
-  // across the boundary from one row block to the next.
-  const int64_t rows_per_wg = 4 * 16 * TM;
-  const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
-  int64_t blk = blockIdx.x;
-  if ((blk * 4 + wave) * (16 * TM) >= g.M) return;  // no barrier follows
-  int64_t rb[TM];
-  f32x4 x0[TM], x1[TM];
-#pragma unroll
-  for (int t = 0; t < TM; ++t) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
-    const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
-    rb[t] = row0 + t * 16 + r16 < g.M ? (hi | rlo) : -1;
-    x0[t] = load_kr4<AM>(A, rb[t], grp * 8, kl[0], kl[1], g);
-    x1[t] = load_kr4<AM>(A, rb[t], grp * 8 + 4, kl[2], kl[3], g);
-  }
-  while (true) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
-    const int64_t nxt = blk + gridDim.x;
-    const int64_t row0n = (nxt * 4 + wave) * (16 * TM);
-    const bool has_next = nxt < nblk && row0n < g.M;
-    f32x4 acc[TM][NTW];
-#pragma unroll
-    for (int t = 0; t < TM; ++t)
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) acc[t][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    int64_t rbn[TM];
-    for (int kc = 0; kc < g.KC; ++kc) {
-      f32x4 y0[TM], y1[TM];
-      if (kc + 1 < g.KC) {
-        const int kr0 = (kc + 1) * 32 + grp * 8;
-        const int64_t kh = k_offset(16 * (kc + 1), g);  // wave-uniform
-#pragma unroll
-        for (int t = 0; t < TM; ++t) {
-          y0[t] = load_kr4<AM>(A, rb[t], kr0, kh | kl[0], kh | kl[1], g);
-          y1[t] = load_kr4<AM>(A, rb[t], kr0 + 4, kh | kl[2], kh | kl[3], g);
-        }
-      } else if (has_next) {
-#pragma unroll
-        for (int t = 0; t < TM; ++t) {
-          const int64_t hi = row_hi((row0n >> 4) + t, g);
-          rbn[t] = row0n + t * 16 + r16 < g.M ? (hi | rlo) : -1;
-          y0[t] = load_kr4<AM>(A, rbn[t], grp * 8, kl[0], kl[1], g);
-          y1[t] = load_kr4<AM>(A, rbn[t], grp * 8 + 4, kl[2], kl[3], g);
-        }
-      }
-      vec ahi[TM], alo[TM];
-      float inv_a[TM];
-#pragma unroll
-      for (int t = 0; t < TM; ++t) {
-        const float x[8] = {x0[t].x, x0[t].y, x0[t].z, x0[t].w,
-                            x1[t].x, x1[t].y, x1[t].z, x1[t].w};
-        float scale = 1.f;
-        inv_a[t] = 1.f;
-        if (!BF16) {
-          float mx = 0.f;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(x[i]));
-          mx = fmaxf(mx, __shfl_xor(mx, 16));
-          mx = fmaxf(mx, __shfl_xor(mx, 32));
-          if (mx > 0.f) {
-            int ex;
-            frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
-            scale = ldexpf(1.f, 14 - ex);
-            inv_a[t] = ldexpf(1.f, ex - 14);
-          }
-        }
-        u16x8 h, l;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float xs = x[i] * scale;
-          float back, dummy;
-          h[i] = S::cvt(xs, &back);
-          l[i] = S::cvt(xs - back, &dummy);
-        }
-        __builtin_memcpy(&ahi[t], &h, 16);
-        __builtin_memcpy(&alo[t], &l, 16);
-      }
-#pragma unroll
-      for (int n = 0; n < NTW; ++n) {
-        if (n < ntw) {
-          u16x8 bh, bl;
-          if (BLDS) {
-            const size_t fo = ((size_t)(kc * NTW + n) * 64 + lane) * 8;
-            bh = *(const u16x8*)(sBh + fo);
-            bl = *(const u16x8*)(sBl + fo);
-          } else {
-            const size_t fo = ((size_t)(kc * g.NT + nt0 + n) * 64 + lane) * 8;
-            bh = *(const u16x8*)(Bh + fo);
-            bl = *(const u16x8*)(Bl + fo);
-          }
-          vec vbh, vbl;
-          __builtin_memcpy(&vbh, &bh, 16);
-          __builtin_memcpy(&vbl, &bl, 16);
-          if (BF16) {
-            // no scale: the three products accumulate in place
-#pragma unroll
-            for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbh, ahi[t], acc[t][n]);
-#pragma unroll
-            for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbl, ahi[t], acc[t][n]);
-#pragma unroll
-            for (int t = 0; t < TM; ++t) acc[t][n] = S::mfma(vbh, alo[t], acc[t][n]);
-          } else {
-            f32x4 part3[TM];
-#pragma unroll
-            for (int t = 0; t < TM; ++t)
-              part3[t] = S::mfma(vbh, ahi[t], f32x4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbl, ahi[t], part3[t]);
-#pragma unroll
-            for (int t = 0; t < TM; ++t) part3[t] = S::mfma(vbh, alo[t], part3[t]);
-#pragma unroll
-            for (int t = 0; t < TM; ++t) acc[t][n] += part3[t] * inv_a[t];
-          }
-        }
-      }
-      if (kc + 1 < g.KC || has_next) {
-#pragma unroll
-        for (int t = 0; t < TM; ++t) {
-          x0[t] = y0[t];
-          x1[t] = y1[t];
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int64_t row = row0 + t * 16 + r16;
-      if (row >= g.M) continue;
-#pragma unroll
-      for (int n = 0; n < NTW; ++n)
-        if (n < ntw) store_nr4<CM>(C, row, (nt0 + n) * 16 + grp * 4, acc[t][n] * inv_b, g);
-    }
-    if (!has_next) break;
-    blk = nxt;
-#pragma unroll
-    for (int t = 0; t < TM; ++t) rb[t] = rbn[t];
+  const uint16_t* Bhs = BLDS ? (const uint16_t*)sBh : Bh;
+  const uint16_t* Bls = BLDS ? (const uint16_t*)sBl : Bl;
+  // KC is a power of two; the ring holds min(2, KC) chunks of 32 reals per
+  // row (one for the small partial shapes that run without FULL)
+  if constexpr (FULL) {
+    if (g.KC >= 2)
+      split_rows<2, TM, NTW, BF16, AM, CM, BLDS, FULL>(A, Bhs, Bls, inv_b, C, g, wave, lane, nt0,
+                                                       ntw);
+    else
+      split_rows<1, TM, NTW, BF16, AM, CM, BLDS, FULL>(A, Bhs, Bls, inv_b, C, g, wave, lane, nt0,
+                                                       ntw);
+  } else {
+    split_rows<1, TM, NTW, BF16, AM, CM, BLDS, FULL>(A, Bhs, Bls, inv_b, C, g, wave, lane, nt0,
+                                                     ntw);
   }
 }
 
-template <int TM, int NTW, int BF16, int AM, int CM>
-static void launch_split_t(const LaunchCtx& c) {
-  const dim3 grid = gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks);
+template <int TM, int NTW, int BF16, int AM, int CM, int FULL>
+static void launch_split_f(const LaunchCtx& c, const dim3& grid) {
   const size_t lds = (size_t)c.g.KC * NTW * 512 * 2 * 2;
   if (lds <= (size_t)kLdsBudget && c.sch.lds != 0)
-    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1>), grid, dim3(256), lds,
-                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1, FULL>), grid, dim3(256),
+                       lds, c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else
-    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 0>), grid, dim3(256), 0,
-                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 0, FULL>), grid, dim3(256),
+                       0, c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+}
+
+// Whole shapes run the requested schedule without predicates; partial ones
+// run one generic predicated kernel with one row block per wave.
+template <int TM, int NTW, int BF16, int AM, int CM>
+static void launch_split_t(const LaunchCtx& c) {
+  if constexpr (CM == 1) {
+    if (gemm_full(c.g, TM, NTW, CM, 32)) {
+      launch_split_f<TM, NTW, BF16, AM, CM, 1>(c, gemm_grid(c.g, TM, NTW, c.nz, c.sch.blocks));
+      return;
+    }
+  }
+  launch_split_f<1, NTW, BF16, AM, CM, 0>(c, gemm_grid(c.g, 1, NTW, c.nz, c.sch.blocks));
 }
 
 template <int BF16, int AM, int CM>
