@@ -82,21 +82,20 @@ def batched_workload(steps: int, tune_cache=None):
     import torch
 
     from paper_2005_06787_amd import Batch, Plan, planner
-    from workloads import tensors
+    from workloads import configs, tensors
     from workloads.circuits import block_qubits, make_circuit
 
-    cycles = [10, 11, 12, 13, 14, 10, 12, 14]
-    widths = [20, 21, 22, 23, 24, 21, 22, 24]
+    cfg = configs.BATCH_5X8
     plans, ranges, flops = [], [], 0.0
     t0 = time.perf_counter()
-    for j, (cyc, w) in enumerate(zip(cycles, widths)):
-        circ = make_circuit(5, 8, cyc, 400 + j)
-        oq = block_qubits(5, 8, range(0, 2), range(5, 8))
-        pre = tensors.split_open_prefix(40, oq, 1400 + j)
+    for j, (cyc, w) in enumerate(zip(cfg["cycles"], cfg["widths"])):
+        circ = make_circuit(cfg["rows"], cfg["cols"], cyc, cfg["circuit_seed0"] + j)
+        oq = block_qubits(cfg["rows"], cfg["cols"], cfg["open_rows"], cfg["open_cols"])
+        pre = tensors.split_open_prefix(circ["n_qubits"], oq, cfg["prefix_seed0"] + j)
         closed = dict(zip(pre["closed"], pre["closed_bits"]))
         net = planner.plan_circuit(circ, oq, closed, max_width=w, trials=8, seed=j)
         plan = Plan(net)
-        n = min(512, 1 << plan.n_sliced)
+        n = min(cfg["slices_each"], 1 << plan.n_sliced)
         group = min(n, max(1, (8 << 30) // plan.workspace_bytes(1)))
         plan.tune(slices_in_flight=group, reps=2, cache_path=tune_cache)
         plans.append(plan)
@@ -105,7 +104,6 @@ def batched_workload(steps: int, tune_cache=None):
         log(f"batched circuit {j}: {cyc} cycles, width {net['stats']['peak_width']}, "
             f"{len(net['sliced_labels'])} sliced labels, group {group}")
     log(f"batched workload planned and tuned in {time.perf_counter() - t0:.1f} s")
-    ws = sum(0 for _ in plans)  # noqa: F841
     ws_bytes = len(plans) * max(p.workspace_bytes(min(r[1], max(1, (8 << 30) // p.workspace_bytes(1))))
                                 for p, r in zip(plans, ranges))
     batch = Batch(plans, ranges, ws_bytes=ws_bytes)
@@ -165,6 +163,52 @@ def isolated_stem(steps: int, tune_cache=None):
     out["flops_per_chain"] = summ["flops_per_slice"]
     out["bytes_per_chain"] = summ["bytes_per_slice"]
     del x
+    torch.cuda.empty_cache()
+    return out
+
+
+def slice_53q(steps: int, tune_cache=None):
+    """One slice of the 53-qubit, 20-cycle circuit at its full per-slice
+    width (stem up to 2^30): slice 0 of the width-30 scheme, FP32 against
+    split FP16."""
+    import torch
+
+    from paper_2005_06787_amd import Plan, planner
+    from workloads import configs
+
+    cfg = configs.C5_53Q_M20
+    t0 = time.perf_counter()
+    circ, oq, closed = configs.circuit_case(cfg)
+    pb = planner.CircuitProblem(circ, oq, closed)
+    order, sliced, peak, tc = planner.find_scheme(pb.tlabels, cfg["order_trials"],
+                                                  cfg["order_seed"], max_width=cfg["max_width"],
+                                                  forbid=pb.forbid)
+    net = planner.scheme_network(pb, order, sliced)
+    log(f"53-qubit scheme planned in {time.perf_counter() - t0:.1f} s: {len(sliced)} sliced "
+        f"labels, peak width {peak}, {len(net['branches'])} steps")
+    out = {"workload": f"53 qubits (6x9 grid less one site), 20 cycles, slice 0 of a width-"
+                       f"{peak} scheme with {len(sliced)} sliced labels, {len(net['branches'])} "
+                       f"steps"}
+    for precision in ("fp32", "split_fp16"):
+        plan = Plan(net, precision=precision)
+        summ = plan.summary()
+        plan.tune(slices_in_flight=1, reps=1, cache_path=tune_cache)
+        res = plan.contract(0, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.contract(0, 1, out=res)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[precision] = {"ms_per_slice": round(dt * 1e3, 3),
+                          "tflops": round(summ["flops_per_slice"] / dt / 1e12, 2),
+                          "algorithmic_gbs": round(summ["bytes_per_slice"] / dt / 1e9, 1)}
+        log(f"53-qubit slice {precision}: {dt * 1e3:.1f} ms, "
+            f"{summ['flops_per_slice'] / dt / 1e12:.1f} TFLOP/s")
+        del res
+        plan.close()
+    out["flops_per_slice"] = summ["flops_per_slice"]
+    out["bytes_per_slice"] = summ["bytes_per_slice"]
     torch.cuda.empty_cache()
     return out
 
@@ -283,7 +327,8 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     net, cfg = make_net()
-    log(f"plan made in {time.perf_counter() - t0:.1f} s: {net['stats']}")
+    log(f"plan made in {time.perf_counter() - t0:.1f} s: "
+        f"{ {k: v for k, v in net['stats'].items() if k != 'order'} }")
     stream = torch.cuda.current_stream()
 
     results = {}
@@ -362,6 +407,7 @@ def main():
     if not args.no_extra:
         line["isolated_stem_2e30"] = isolated_stem(3, args.tune_cache)
         line["batched_8_circuits"] = batched_workload(3, args.tune_cache)
+        line["slice_53q_m20"] = slice_53q(3, args.tune_cache)
     print(json.dumps(line), flush=True)
 
 

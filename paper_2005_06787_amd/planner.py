@@ -65,6 +65,16 @@ class _Order:
             stems.append(frozenset(stem))
         self.stems = stems        # stem after absorbing order[0..k]
         self.unions = unions      # labels of step k (stem before + tensor)
+        # the same sets as 0/1 matrices over the sorted labels
+        self.labels = sorted(set().union(*stems, *unions))
+        col = {x: i for i, x in enumerate(self.labels)}
+        self.smat = np.zeros((len(stems), len(self.labels)), dtype=np.int64)
+        self.umat = np.zeros((len(unions), len(self.labels)), dtype=np.int64)
+        for k, st in enumerate(stems):
+            self.smat[k, [col[x] for x in st]] = 1
+        for k, u in enumerate(unions):
+            self.umat[k, [col[x] for x in u]] = 1
+        self.col = col
 
     def widths(self, sliced=frozenset()):
         return [len(s - sliced) for s in self.stems]
@@ -100,32 +110,47 @@ def _linear_order(tlabels, owners, rng, noise=0.5):
     return order
 
 
-def greedy_slice(od: _Order, n_sliced=None, max_width=None, forbid=()):
-    """Greedy slicing of a linear order (ties: lowest label)."""
-    sliced = set()
-    forbid = set(forbid)
+def greedy_slice(od: _Order, n_sliced=None, max_width=None, forbid=(), rng=None, top: int = 3):
+    """Greedy slicing of a linear order (§4, §A.2 dynamic slicing).
+
+    Each pick adds, among the labels of the widest stems, the one whose
+    removal gives the smallest (peak width, tc); ties go to the lowest
+    label.  With ``rng`` the pick is uniform among the ``top`` best (the
+    randomised variant that draws candidate slicing sets).  All candidates
+    of a pick are scored at once: with w_k the width of stem k and u_k the
+    size of step k's label set (both without the sliced labels), slicing
+    label x gives peak max_k (w_k - [x in stem k]) and
+    tc = 2 tc - 2^|E_s| sum_{k: x in step k} 2^u_k (§A.1).
+    """
+    sliced = []
+    fb = np.zeros(len(od.labels), dtype=bool)
+    for x in forbid:
+        if x in od.col:
+            fb[od.col[x]] = True
+    taken = np.zeros(len(od.labels), dtype=bool)
+    w = od.smat.sum(axis=1)
+    u = od.umat.sum(axis=1)
     while True:
-        w = od.widths(frozenset(sliced))
-        peak = max(w)
+        peak = int(w.max())
         if n_sliced is not None and len(sliced) >= n_sliced:
             break
         if n_sliced is None and (max_width is None or peak <= max_width):
             break
-        cands = set()
-        for s, wk in zip(od.stems, w):
-            if wk == peak:
-                cands |= set(s)
-        cands -= sliced
-        cands -= forbid
-        if not cands:
+        cand = od.smat[w == peak].any(axis=0) & ~taken & ~fb
+        idx = np.nonzero(cand)[0]
+        if not len(idx):
             break
-        best, best_key = None, None
-        for x in sorted(cands):
-            trial = frozenset(sliced | {x})
-            key = (max(od.widths(trial)), od.tc(trial))
-            if best_key is None or key < best_key:
-                best, best_key = x, key
-        sliced.add(best)
+        new_peak = (w[:, None] - od.smat[:, idx]).max(axis=0)
+        pw = np.exp2(u.astype(np.float64))
+        tc_now = (2.0 ** len(sliced)) * pw.sum()
+        new_tc = 2.0 * tc_now - (2.0 ** len(sliced)) * (pw @ od.umat[:, idx])
+        keys = sorted(zip(new_peak.tolist(), new_tc.tolist(), [od.labels[i] for i in idx], idx))
+        pick = keys[0] if rng is None else keys[int(rng.integers(min(top, len(keys))))]
+        i = pick[3]
+        taken[i] = True
+        sliced.append(od.labels[i])
+        w = w - od.smat[:, i]
+        u = u - od.umat[:, i]
     return sorted(sliced)
 
 
@@ -147,6 +172,22 @@ def find_scheme(tlabels, trials: int, seed: int, n_sliced=None, max_width=None, 
             best = (key, order, sl)
     (peak, tc), order, sl = best
     return order, sl, peak, tc
+
+
+def candidate_slicings(tlabels, order, n: int, seed: int, n_sliced=None, max_width=None,
+                       forbid=(), top: int = 3):
+    """n slicing sets of one order from the randomised greedy slicer
+    (distinct sets only, in the order drawn)."""
+    od = _Order(tlabels, order)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, seen = [], set()
+    for _ in range(n):
+        sl = tuple(greedy_slice(od, n_sliced=n_sliced, max_width=max_width, forbid=forbid,
+                                rng=rng, top=top))
+        if sl not in seen:
+            seen.add(sl)
+            out.append(list(sl))
+    return out
 
 
 def _group_labels(tlabels, group):
@@ -200,25 +241,41 @@ def _contract_group(tensors, group, keep):
     return acc
 
 
-def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=(), *,
-                 n_sliced=None, max_width=None, trials: int = 64, seed: int = 0,
-                 init_rank: int = 12, max_branch_rank: int = 12, merge: bool = True) -> dict:
-    """Sliced stem network of a circuit's amplitudes.
+def _group_label_list(tensors, group, keep):
+    """Labels (in order) of _contract_group's result, without the data."""
+    out = list(tensors[group[0]][0])
+    for j in group[1:]:
+        lb = tensors[j][0]
+        summed = {x for x in out if x in lb and x not in keep}
+        out = [x for x in out if x not in summed] + [x for x in lb if x not in out]
+    return out
 
-    ``open_qubits`` stay open (result index, first qubit most significant),
-    ``proj_qubits`` are fixed per batch entry (projected assignment bits in
-    the same order), the other qubits are closed with ``closed_bits``.
-    Returns the network dictionary plus a "stats" entry.
+
+class CircuitProblem:
+    """A circuit's simplified network and the label sets the planner orders
+    (projected labels excluded; open labels may not be sliced)."""
+
+    def __init__(self, circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=()):
+        self.net = simplify(circuit_network(circuit, open_qubits, closed_bits, proj_qubits))
+        ids = sorted(self.net.tensors)
+        self.tensors = [self.net.tensors[i] for i in ids]
+        self.proj = set(self.net.proj_labels)
+        self.tlabels = [frozenset(x for x in lab if x not in self.proj)
+                        for lab, _ in self.tensors]
+        self.forbid = set(self.net.open_labels)
+
+
+def scheme_network(pb: CircuitProblem, order, sliced, *, init_rank: int = 12,
+                   max_branch_rank: int = 12, merge: bool = True, with_data: bool = True,
+                   stats: dict | None = None) -> dict:
+    """The stem network of a scheme (order, sliced labels) of a problem.
+
+    Without data the tensors carry their labels only (for ranking schemes
+    by their step shapes); with data the initial stem and the branches are
+    contracted on the host in FP64 and stored as complex64.
     """
-    net = simplify(circuit_network(circuit, open_qubits, closed_bits, proj_qubits))
-    ids = sorted(net.tensors)
-    tensors = [net.tensors[i] for i in ids]
-    proj = set(net.proj_labels)
-    tlabels = [frozenset(x for x in lab if x not in proj) for lab, _ in tensors]
-    forbid = set(net.open_labels)
-    order, sliced, peak, tc = find_scheme(tlabels, trials, seed, n_sliced=n_sliced,
-                                          max_width=max_width, forbid=forbid)
-    fixed = set(sliced) | proj
+    tlabels = pb.tlabels
+    fixed = set(sliced) | pb.proj
     # initial stem: absorb while the (unfixed) rank stays within init_rank
     n_init = 1
     stem_lab = set(tlabels[order[0]]) - fixed
@@ -230,19 +287,44 @@ def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=()
         n_init += 1
     groups = group_branches(tlabels, order, n_init, fixed, max_branch_rank, merge)
     keep = set(sliced)
-    stem = _contract_group(tensors, order[:n_init], keep)
+    if with_data:
+        stem = _contract_group(pb.tensors, order[:n_init], keep)
+        stem_d = {"labels": [int(x) for x in stem[0]], "data": stem[1].astype(np.complex64)}
+    else:
+        stem_d = {"labels": [int(x) for x in _group_label_list(pb.tensors, order[:n_init], keep)]}
     branches = []
     for g in groups:
-        lab, data = _contract_group(tensors, g, keep)
-        branches.append({"labels": [int(x) for x in lab], "data": data.astype(np.complex64)})
+        if with_data:
+            lab, data = _contract_group(pb.tensors, g, keep)
+            branches.append({"labels": [int(x) for x in lab], "data": data.astype(np.complex64)})
+        else:
+            branches.append({"labels": [int(x) for x in _group_label_list(pb.tensors, g, keep)]})
+    st = dict(stats or {})
+    st.update({"n_tensors": len(pb.tensors), "n_branches": len(branches), "n_init": n_init})
     return {
-        "open_labels": [int(x) for x in net.open_labels],
-        "sliced_labels": [int(x) for x in sliced],
-        "proj_labels": [int(x) for x in net.proj_labels],
-        "stem": {"labels": [int(x) for x in stem[0]], "data": stem[1].astype(np.complex64)},
+        "open_labels": [int(x) for x in pb.net.open_labels],
+        "sliced_labels": [int(x) for x in sorted(sliced)],
+        "proj_labels": [int(x) for x in pb.net.proj_labels],
+        "stem": stem_d,
         "branches": branches,
-        "stats": {"peak_width": int(peak), "tc": float(tc),
-                  "log2_tc": float(math.log2(tc)) if tc > 0 else 0.0,
-                  "n_tensors": len(tensors), "n_branches": len(branches),
-                  "n_init": n_init},
+        "stats": st,
     }
+
+
+def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=(), *,
+                 n_sliced=None, max_width=None, trials: int = 64, seed: int = 0,
+                 init_rank: int = 12, max_branch_rank: int = 12, merge: bool = True) -> dict:
+    """Sliced stem network of a circuit's amplitudes.
+
+    ``open_qubits`` stay open (result index, first qubit most significant),
+    ``proj_qubits`` are fixed per batch entry (projected assignment bits in
+    the same order), the other qubits are closed with ``closed_bits``.
+    Returns the network dictionary plus a "stats" entry.
+    """
+    pb = CircuitProblem(circuit, open_qubits, closed_bits, proj_qubits)
+    order, sliced, peak, tc = find_scheme(pb.tlabels, trials, seed, n_sliced=n_sliced,
+                                          max_width=max_width, forbid=pb.forbid)
+    stats = {"peak_width": int(peak), "tc": float(tc),
+             "log2_tc": float(math.log2(tc)) if tc > 0 else 0.0, "order": list(order)}
+    return scheme_network(pb, order, sliced, init_rank=init_rank,
+                          max_branch_rank=max_branch_rank, merge=merge, stats=stats)

@@ -24,8 +24,13 @@ N_FEATURES = C.STEM_N_FEATURES
 
 def plan_steps(net: dict, precision: str = "fp32") -> list:
     """Step infos (ctypes structs) of a network, on the host."""
+    # the step shapes depend on the labels only: absent data is zeros
     if "data" not in net["stem"]:
         net = dict(net, stem=dict(net["stem"], data=np.zeros(1 << len(net["stem"]["labels"]))))
+    if any("data" not in b for b in net.get("branches", [])):
+        net = dict(net, branches=[b if "data" in b else
+                                  dict(b, data=np.zeros(1 << len(b["labels"]), np.complex64))
+                                  for b in net["branches"]])
     d = _Desc(net, precision)
     n = ctypes.c_int32()
     C.check(C.lib().stem_plan_steps(ctypes.byref(d.desc), None, 0, ctypes.byref(n)))
@@ -195,3 +200,56 @@ def fit(x: np.ndarray, us: np.ndarray, hidden: int = 64, steps: int = 3000, lr: 
     m.set_scaling(xm, inv, float(t.mean()), float(max(t.std(), 1e-3)))
     m.train(x, t.astype(np.float32), steps, lr)
     return m
+
+
+def scheme_seconds(net: dict, precision: str = "fp32", slices_in_flight: int = 1,
+                   model: "RuntimeMLP | None" = None) -> dict:
+    """Predicted contraction time of a scheme's network (labels suffice).
+
+    Returns seconds per slice and for all 2^|E_s| slices (§A.1: the cost of a
+    sliced scheme is the per-slice cost times the number of slices), from
+    the analytic model and, when ``model`` is given, from the MLP: its
+    product-launch times (a launch carries ``slices_in_flight`` slices) plus
+    the analytic cost of the permutes and the final accumulation.
+    """
+    steps = plan_steps(net, precision)
+    n_slices = 2.0 ** len(net["sliced_labels"])
+    g = max(1, int(slices_in_flight))
+    per_group = analytic_seconds(steps, precision, g, g)
+    out = {"analytic_slice_s": per_group / g, "analytic_total_s": per_group / g * n_slices}
+    if model is not None:
+        # analytic cost of everything but the product launches
+        bare = []
+        for s in steps:
+            c = C.stem_step_info()
+            ctypes.memmove(ctypes.byref(c), ctypes.byref(s), ctypes.sizeof(c))
+            c.permuted = 0
+            bare.append(c)
+        launch = analytic_seconds([], precision, g, g)
+        rest = per_group - (analytic_seconds(bare, precision, g, g) - launch)
+        pred_us = np.exp(model.predict(features(steps, precision, g))) if steps else np.zeros(0)
+        mlp_group = float(pred_us.sum()) * 1e-6 + rest
+        out["mlp_slice_s"] = mlp_group / g
+        out["mlp_total_s"] = mlp_group / g * n_slices
+    return out
+
+
+def spearman(a, b) -> float:
+    """Spearman rank correlation of two sequences (average ranks for ties)."""
+    def ranks(x):
+        x = np.asarray(x, dtype=np.float64)
+        order = np.argsort(x, kind="stable")
+        r = np.empty(len(x))
+        i = 0
+        while i < len(x):
+            j = i
+            while j + 1 < len(x) and x[order[j + 1]] == x[order[i]]:
+                j += 1
+            r[order[i:j + 1]] = 0.5 * (i + j)
+            i = j + 1
+        return r
+    ra, rb = ranks(a), ranks(b)
+    ra -= ra.mean()
+    rb -= rb.mean()
+    den = math.sqrt(float((ra * ra).sum() * (rb * rb).sum()))
+    return float((ra * rb).sum() / den) if den > 0 else 0.0

@@ -80,3 +80,57 @@ def test_slicing_cost_identity():
     od2 = planner._Order(removed, order)
     assert tc == pytest.approx(8 * od2.tc())
     assert peak == max(od2.widths())
+
+
+def _problem():
+    c = wc.make_circuit(4, 5, 8, seed=1)
+    open_q = wc.block_qubits(4, 5, range(0, 2), range(2, 5))
+    pre = wt.split_open_prefix(20, open_q, 1001)
+    return planner.CircuitProblem(c, open_q, dict(zip(pre["closed"], pre["closed_bits"])))
+
+
+def test_candidate_slicings_meet_the_width_and_are_distinct():
+    pb = _problem()
+    order, sliced, peak, tc = planner.find_scheme(pb.tlabels, 8, 0, max_width=9,
+                                                  forbid=pb.forbid)
+    od = planner._Order(pb.tlabels, order)
+    cands = planner.candidate_slicings(pb.tlabels, order, 40, 5000, max_width=9,
+                                       forbid=pb.forbid)
+    assert len(cands) >= 2
+    assert len({tuple(c) for c in cands}) == len(cands)
+    for c in cands:
+        assert max(od.widths(frozenset(c))) <= 9
+        assert not set(c) & pb.forbid
+    # the randomised slicer restricted to the best pick is the greedy one
+    assert planner.candidate_slicings(pb.tlabels, order, 3, 1, max_width=9, forbid=pb.forbid,
+                                      top=1) == [sliced]
+
+
+def test_vectorised_slice_scores_equal_direct_evaluation():
+    """The greedy slicer scores a pick by peak width and tc computed from
+    per-step counts; recomputing both from the label sets agrees."""
+    pb = _problem()
+    order, _, _, _ = planner.find_scheme(pb.tlabels, 2, 3, n_sliced=0, forbid=pb.forbid)
+    od = planner._Order(pb.tlabels, order)
+    sl = planner.greedy_slice(od, n_sliced=5, forbid=pb.forbid)
+    # the greedy pick at each stage is the minimum of the direct scores
+    chosen = []
+    for _ in range(5):
+        w = od.widths(frozenset(chosen))
+        peak = max(w)
+        cands = sorted(set().union(*[s for s, wk in zip(od.stems, w) if wk == peak])
+                       - set(chosen) - pb.forbid)
+        best = min(cands, key=lambda x: (max(od.widths(frozenset(chosen + [x]))),
+                                         od.tc(frozenset(chosen + [x])), x))
+        chosen.append(best)
+    assert sorted(chosen) == sl
+
+
+def test_shapes_only_network_has_the_data_network_labels():
+    pb = _problem()
+    order, sliced, _, _ = planner.find_scheme(pb.tlabels, 4, 0, n_sliced=3, forbid=pb.forbid)
+    a = planner.scheme_network(pb, order, sliced)
+    b = planner.scheme_network(pb, order, sliced, with_data=False)
+    assert a["stem"]["labels"] == b["stem"]["labels"]
+    assert [x["labels"] for x in a["branches"]] == [x["labels"] for x in b["branches"]]
+    assert "data" not in b["stem"] and all("data" not in x for x in b["branches"])
