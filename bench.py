@@ -47,13 +47,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic():
+def recorded_traffic(bytes_per_launch: float):
+    """HBM bytes per product launch measured by the counters, when the
+    record is of these kernel sources and of launches of this size."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    if abs(rec.get("algorithmic_bytes_per_launch", 0) - bytes_per_launch) > 1e-6 * bytes_per_launch:
         return None
     return rec.get("bytes_per_launch")
 
@@ -251,7 +255,7 @@ def roofline(plan):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": recorded_traffic(),
+        "traffic": recorded_traffic(g_bytes / launches),
         "slices_per_launch": nz,
         "bytes_per_launch": g_bytes / launches,
         "avg_launch_us": g_us / launches,

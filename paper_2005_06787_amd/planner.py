@@ -16,10 +16,11 @@ slicing scheme (E_s, T) whose tree T is a stem (§A.1, §A.2):
    label), until the width target or the sliced-label count is met.
    tc((E_s, T)) = 2^|E_s| * sum over steps of 2^|E_step \\ E_s| (§A.1).
 4. The first tensors of the order are pre-contracted into the initial stem
-   while its rank stays small; the rest are grouped into branches, merging
-   consecutive tensors while a roofline time model of the step says one
-   larger product is faster than two (§A.3, branch merging), up to a
-   branch rank limit.
+   while its rank stays small; the rest are grouped into branches of
+   consecutive tensors (§A.3, branch merging), up to a branch rank limit.
+   The merge points minimise the summed step time of a cost model (a
+   roofline of the rates the kernels sustain, or the learned model), by
+   dynamic programming over the order.
 5. Branches and the initial stem are contracted on the host in FP64 and
    stored as complex64 (§A.3: computed once, shared by all slices).
 """
@@ -198,8 +199,21 @@ def _group_labels(tlabels, group):
 
 
 def group_branches(tlabels, order, n_init: int, fixed: set, max_branch_rank: int = 12,
-                   merge: bool = True):
-    """Split order[n_init:] into consecutive groups (merged branches)."""
+                   merge=True, step_cost=None):
+    """Split order[n_init:] into consecutive groups (merged branches).
+
+    Without ``step_cost``: greedy, a tensor joins the current group while
+    one merged product is modelled no slower than two (``step_time``).
+    With ``step_cost(r_in, s, f) -> seconds``: the partition that minimises
+    the summed cost, by dynamic programming over the order (the stem
+    before a group does not depend on how earlier tensors were grouped, so
+    the optimum over prefixes composes); groups end within
+    ``max_branch_rank`` unfixed labels and never pass through more than 4
+    labels above it while the host contracts them in order.
+    """
+    if step_cost is not None and merge:
+        return _group_branches_dp(tlabels, order, n_init, fixed, max_branch_rank, step_cost)
+    merge = bool(merge)
     stem = _group_labels(tlabels, order[:n_init]) - fixed
     groups = []
     cur = []
@@ -234,6 +248,51 @@ def group_branches(tlabels, order, n_init: int, fixed: set, max_branch_rank: int
     return groups
 
 
+def _group_branches_dp(tlabels, order, n_init, fixed, max_branch_rank, step_cost):
+    seq = list(order[n_init:])
+    n = len(seq)
+    labs = [frozenset(tlabels[j] - fixed) for j in seq]
+    stems = [frozenset(_group_labels(tlabels, order[:n_init]) - fixed)]
+    for t in labs:
+        stems.append(stems[-1] ^ t)
+    best = [0.0] + [math.inf] * n
+    back = [0] * (n + 1)
+    for i in range(n):
+        if best[i] == math.inf:
+            continue
+        st = stems[i]
+        g = set()
+        for j in range(i, n):
+            g ^= labs[j]
+            if j > i and len(g) > max_branch_rank:
+                if len(g) > max_branch_rank + 4:   # the host contracts groups in order
+                    break
+                continue
+            c = best[i] + step_cost(len(st), len(st & g), len(g - st))
+            if c < best[j + 1]:
+                best[j + 1], back[j + 1] = c, i
+    groups = []
+    j = n
+    while j > 0:
+        i = back[j]
+        groups.append(seq[i:j])
+        j = i
+    return groups[::-1]
+
+
+def roofline_step_cost(hbm_bytes_per_s: float = 5.0e12, flops_per_s: float = 1.2e14,
+                       launch_s: float = 4e-6, slices_in_flight: int = 128):
+    """step_cost(r_in, s, f) of one slice on a roofline: max(bytes / bandwidth,
+    flops / rate) plus the launch shared by the slices in flight.  The
+    defaults are the rates the product kernels sustain on one MI355X in
+    FP32 (streaming 5 TB/s, 120 TFLOP/s on MFMA-bound shapes)."""
+    def cost(r_in, s, f):
+        m, k, n = 2.0 ** (r_in - s), 2.0 ** s, 2.0 ** f
+        return (max(8.0 * (m * k + m * n + k * n) / hbm_bytes_per_s,
+                    8.0 * m * k * n / flops_per_s) + launch_s / slices_in_flight)
+    return cost
+
+
 def _contract_group(tensors, group, keep):
     acc = tensors[group[0]]
     for j in group[1:]:
@@ -266,9 +325,15 @@ class CircuitProblem:
 
 
 def scheme_network(pb: CircuitProblem, order, sliced, *, init_rank: int = 12,
-                   max_branch_rank: int = 12, merge: bool = True, with_data: bool = True,
-                   stats: dict | None = None) -> dict:
+                   max_branch_rank: int = 12, merge: str = "dp", with_data: bool = True,
+                   stats: dict | None = None, step_cost=None) -> dict:
     """The stem network of a scheme (order, sliced labels) of a problem.
+
+    Branch merging (§A.3): ``merge`` "dp" picks the merge points that
+    minimise the summed ``step_cost`` (default: ``roofline_step_cost()``;
+    the MLP's predictions through ``runtime_model.mlp_step_cost``), "greedy"
+    merges while the built-in roofline says one larger product is no
+    slower than two, "none" keeps one branch per tensor.
 
     Without data the tensors carry their labels only (for ranking schemes
     by their step shapes); with data the initial stem and the branches are
@@ -285,7 +350,12 @@ def scheme_network(pb: CircuitProblem, order, sliced, *, init_rank: int = 12,
             break
         stem_lab = nxt
         n_init += 1
-    groups = group_branches(tlabels, order, n_init, fixed, max_branch_rank, merge)
+    if merge == "dp":
+        groups = group_branches(tlabels, order, n_init, fixed, max_branch_rank, True,
+                                step_cost or roofline_step_cost())
+    else:
+        groups = group_branches(tlabels, order, n_init, fixed, max_branch_rank,
+                                merge == "greedy")
     keep = set(sliced)
     if with_data:
         stem = _contract_group(pb.tensors, order[:n_init], keep)
@@ -313,7 +383,8 @@ def scheme_network(pb: CircuitProblem, order, sliced, *, init_rank: int = 12,
 
 def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=(), *,
                  n_sliced=None, max_width=None, trials: int = 64, seed: int = 0,
-                 init_rank: int = 12, max_branch_rank: int = 12, merge: bool = True) -> dict:
+                 init_rank: int = 12, max_branch_rank: int = 12, merge: str = "dp",
+                 step_cost=None) -> dict:
     """Sliced stem network of a circuit's amplitudes.
 
     ``open_qubits`` stay open (result index, first qubit most significant),
@@ -327,4 +398,5 @@ def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=()
     stats = {"peak_width": int(peak), "tc": float(tc),
              "log2_tc": float(math.log2(tc)) if tc > 0 else 0.0, "order": list(order)}
     return scheme_network(pb, order, sliced, init_rank=init_rank,
-                          max_branch_rank=max_branch_rank, merge=merge, stats=stats)
+                          max_branch_rank=max_branch_rank, merge=merge, stats=stats,
+                          step_cost=step_cost)

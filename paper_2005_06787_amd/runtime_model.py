@@ -253,3 +253,20 @@ def spearman(a, b) -> float:
     rb -= rb.mean()
     den = math.sqrt(float((ra * ra).sum() * (rb * rb).sum()))
     return float((ra * rb).sum() / den) if den > 0 else 0.0
+
+
+def mlp_step_cost(model: "RuntimeMLP", precision: str = "fp32", slices_in_flight: int = 128):
+    """step_cost(r_in, s, f) for the planner's branch merging from the MLP:
+    the predicted time of one product launch of that shape (stem read
+    M-fast, output in block order), per slice.  Predictions are cached."""
+    cache = {}
+    g = max(1, int(slices_in_flight))
+
+    def cost(r_in, s, f):
+        key = (r_in, s, f)
+        if key not in cache:
+            st = step_info_from_shape(r_in - s, s, f, 1, 1 if r_in - s >= 4 else 0)
+            us = float(np.exp(model.predict(features([st], precision, g))[0]))
+            cache[key] = us * 1e-6 / g
+        return cache[key]
+    return cost

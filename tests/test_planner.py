@@ -134,3 +134,56 @@ def test_shapes_only_network_has_the_data_network_labels():
     assert a["stem"]["labels"] == b["stem"]["labels"]
     assert [x["labels"] for x in a["branches"]] == [x["labels"] for x in b["branches"]]
     assert "data" not in b["stem"] and all("data" not in x for x in b["branches"])
+
+
+def _grouping_cost(tlabels, order, n_init, fixed, groups, cost, max_rank):
+    stem = set()
+    for j in order[:n_init]:
+        stem ^= tlabels[j] - fixed
+    total = 0.0
+    for g in groups:
+        lab = set()
+        for j in g:
+            lab ^= tlabels[j] - fixed
+        if len(g) > 1 and len(lab) > max_rank:
+            return None
+        total += cost(len(stem), len(stem & lab), len(lab - stem))
+        stem ^= lab
+    return total
+
+
+def test_dp_branch_merging_is_optimal_over_all_partitions():
+    """The merge points the planner picks by dynamic programming give the
+    least summed step cost among all 2^(n-1) partitions of the order into
+    consecutive groups (checked exhaustively on 12 tensors)."""
+    pb = _problem()
+    order, sliced, _, _ = planner.find_scheme(pb.tlabels, 4, 0, n_sliced=2, forbid=pb.forbid)
+    fixed = set(sliced) | pb.proj
+    n_init = len(order) - 12
+    cost = planner.roofline_step_cost(5.0e12, 1.2e14, slices_in_flight=1)
+    max_rank = 6
+    groups = planner.group_branches(pb.tlabels, order, n_init, fixed, max_rank, True, cost)
+    assert [j for g in groups for j in g] == list(order[n_init:])
+    got = _grouping_cost(pb.tlabels, order, n_init, fixed, groups, cost, max_rank)
+    seq = list(order[n_init:])
+    best = None
+    for cuts in range(1 << (len(seq) - 1)):
+        gs, cur = [], [seq[0]]
+        for k in range(1, len(seq)):
+            if (cuts >> (k - 1)) & 1:
+                gs.append(cur)
+                cur = []
+            cur.append(seq[k])
+        gs.append(cur)
+        # the planner also bounds the in-order intermediate rank of a group
+        ok = True
+        for g in gs:
+            lab = set()
+            for j in g:
+                lab ^= pb.tlabels[j] - fixed
+                if len(g) > 1 and len(lab) > max_rank + 4:
+                    ok = False
+        c = _grouping_cost(pb.tlabels, order, n_init, fixed, gs, cost, max_rank) if ok else None
+        if c is not None and (best is None or c < best):
+            best = c
+    assert got == pytest.approx(best, rel=1e-12)
