@@ -217,6 +217,44 @@ def slice_53q(steps: int, tune_cache=None):
     return out
 
 
+def sampling_30q(n_prefixes: int, tune_cache=None):
+    """Frugal rejection sampling on the 30-qubit, 14-cycle circuit: random
+    prefixes of the 24 closed qubits as projected batch entries (64
+    amplitudes each, all 2^10 slices), acceptance min(1, 2^n p / 10)."""
+    import torch
+
+    from paper_2005_06787_amd import Plan, planner, sampling
+    from workloads import configs
+
+    cfg = configs.CIRCUIT_CONFIGS["c2_5x6_m14"]
+    circ, oq, _ = configs.circuit_case(cfg)
+    n = circ["n_qubits"]
+    closed_q = [q for q in range(n) if q not in oq]
+    net = planner.plan_circuit(circ, oq, None, closed_q, n_sliced=cfg["n_sliced"], trials=64,
+                               seed=0)
+    plan = Plan(net)
+    plan.tune(slices_in_flight=plan.default_slices_in_flight(1 << plan.n_sliced), reps=2,
+              cache_path=tune_cache)
+    prefixes = np.random.Generator(np.random.PCG64(4001)).integers(0, 1 << len(closed_q),
+                                                                    n_prefixes)
+    plan.contract(proj=prefixes[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = sampling.sample(plan, n, oq, closed_q, prefixes, 10.0,
+                          np.random.Generator(np.random.PCG64(4002)))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.close()
+    log(f"sampling: {n_prefixes} batches in {dt:.2f} s, {res['n_samples']} samples, "
+        f"XEB {res['xeb']:.3f}")
+    return {"workload": f"30 qubits, 14 cycles, {n_prefixes} random prefixes of the 24 closed "
+                        f"qubits x 64 open amplitudes, 2^10 slices each, M = 10, FP32",
+            "batches_per_s": round(n_prefixes / dt, 3),
+            "samples_per_s": round(res["n_samples"] / dt, 2),
+            "acceptance": round(res["acceptance"], 4), "samples": res["n_samples"],
+            "xeb_of_samples": round(res["xeb"], 4)}
+
+
 def timed_run(plan, steps, warmup, n_slices, stream):
     import torch
 
@@ -412,6 +450,7 @@ def main():
         line["isolated_stem_2e30"] = isolated_stem(3, args.tune_cache)
         line["batched_8_circuits"] = batched_workload(3, args.tune_cache)
         line["slice_53q_m20"] = slice_53q(3, args.tune_cache)
+        line["sampling_30q"] = sampling_30q(8, args.tune_cache)
     print(json.dumps(line), flush=True)
 
 

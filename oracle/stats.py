@@ -9,11 +9,20 @@
   and the unit exponential law, whose density e^{-x} is the Porter-Thomas
   form N e^{-Np} written for x = N p (paper §A.4).
 * ``rel_l2``: ||a - ref||_2 / ||ref||_2 over a whole vector.
+* ``frugal_acceptance`` / ``frugal_xeb``: frugal rejection sampling (paper
+  §3, after Markov et al. 2018) accepts a candidate bitstring x, drawn
+  uniformly, with probability min(1, N p(x) / M); the accepted ones follow
+  q(x) proportional to min(p(x), M / N).  These give, from the ideal
+  probabilities of every bitstring, the acceptance probability of one
+  candidate, sum_x min(1, N p / M) / N, and the XEB of the accepted
+  samples, N sum_x q(x) p(x) - 1.
 
-Pins (tests/test_oracle_stats.py): uniform probabilities give XEB 0 and
-exact exponential quantiles give KS distance ~0; a two-point distribution
-with hand-computed XEB; the 20-qubit random circuit gives collision XEB
-within a statistical window of 1.
+Pins (tests/test_oracle_misc.py, test_oracle_statevector.py): uniform
+probabilities give XEB 0 and exact exponential quantiles give KS distance
+~0; a two-point distribution with hand-computed XEB; the 20-qubit random
+circuit gives collision XEB within a statistical window of 1; the frugal
+XEB tends to the collision XEB as M grows and is 0 when M is below every
+N p (uniform acceptance), with a hand-computed two-point case.
 """
 
 from __future__ import annotations
@@ -31,6 +40,19 @@ def xeb(amps, n_qubits: int) -> float:
 def collision_xeb(amps_all, n_qubits: int) -> float:
     p = np.abs(np.asarray(amps_all, dtype=np.complex128)) ** 2
     return float((2.0 ** n_qubits) * np.sum(p * p) - 1.0)
+
+
+def frugal_acceptance(probs_all, m: float) -> float:
+    p = np.asarray(probs_all, dtype=np.float64)
+    n = p.size
+    return float(np.minimum(1.0, n * p / m).mean())
+
+
+def frugal_xeb(probs_all, m: float) -> float:
+    p = np.asarray(probs_all, dtype=np.float64)
+    n = p.size
+    q = np.minimum(p, m / n)
+    return float(n * np.sum(q * p) / np.sum(q) - 1.0)
 
 
 def porter_thomas_ks(probs, n_states: int) -> float:

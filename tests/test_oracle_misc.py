@@ -158,3 +158,26 @@ def test_adam_first_step():
     step = 0.01 * np.array([0.5, -2.0, 0.0]) / (np.abs([0.5, -2.0, 0.0]) + 1e-8)
     for k in mlp.PARAM_NAMES:
         assert np.allclose(params[k], 1.0 - step, atol=1e-12)
+
+
+def test_frugal_sampling_special_cases():
+    n = 6
+    rng = np.random.Generator(np.random.PCG64(9))
+    a = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    p = np.abs(a) ** 2
+    p /= p.sum()
+    amps = np.sqrt(p)
+    # M above every N p: every candidate is accepted with probability N p / M,
+    # the accepted ones follow p, and their XEB is the collision XEB
+    big = 2.0 * p.max() * p.size
+    assert stats.frugal_xeb(p, big) == pytest.approx(stats.collision_xeb(amps, n), rel=1e-12)
+    assert stats.frugal_acceptance(p, big) == pytest.approx(1.0 / big, rel=1e-12)
+    # M below every N p: every candidate is accepted, uniform samples, XEB 0
+    small = 0.5 * p.min() * p.size
+    assert abs(stats.frugal_xeb(p, small)) < 1e-12
+    assert stats.frugal_acceptance(p, small) == 1.0
+    # two outcomes, p = (0.9, 0.1), N = 2, M = 1: q = (0.5, 0.1) / 0.6,
+    # XEB = 2 (0.5 * 0.9 + 0.1 * 0.1) / 0.6 - 1 = 8/15; acceptance (1 + 0.2) / 2
+    two = np.array([0.9, 0.1])
+    assert stats.frugal_xeb(two, 1.0) == pytest.approx(8.0 / 15.0, rel=1e-12)
+    assert stats.frugal_acceptance(two, 1.0) == pytest.approx(0.6, rel=1e-12)
