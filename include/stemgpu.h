@@ -65,15 +65,19 @@ enum {
  * values; every bond has dimension 2 (§A.1).
  *
  * Label rules checked by stem_plan_validate / stem_plan_create:
- *  - an open label occurs in exactly one tensor;
+ *  - an open label occurs in at least one tensor;
  *  - a sliced or projected label occurs in at least one tensor and is not open;
- *  - every other label occurs in exactly two tensors;
- *  - a label the stem shares with branch i occurs in no later branch
- *    (otherwise it would be a hyperedge: STEM_EUNSUPPORTED);
+ *  - every other label occurs in at least two tensors (more than two: a
+ *    hyperedge, §A.1);
+ *  - a step keeps at most 4 of the labels the stem shares with its branch
+ *    (STEM_EUNSUPPORTED otherwise);
  *  - after the last branch the stem carries exactly the open labels.
  * Step i contracts the stem with branch i over the labels they share (after
  * the sliced and projected labels are fixed), which is one pairwise
- * contraction of §A.1 with time 2^|E_AB| and space 2^|E*_AB|.
+ * contraction of §A.1 with time 2^|E_AB| and space 2^|E*_AB|.  A shared
+ * label that a later branch or the result still carries is kept, not
+ * summed (a batch label: the step is a batched product, one product per
+ * assignment of its batch labels, each with its own branch sub-matrix).
  */
 typedef struct stem_plan_desc {
   int32_t n_open;
@@ -103,9 +107,9 @@ typedef struct stem_step_info {
   int32_t n_free;         /* f: new labels from the branch, N = 2^f */
   int32_t permuted;       /* 1 if a stem permute runs before the product */
   int32_t last_slices;    /* slices covered by the timed launches below (0: none) */
-  int64_t M, K, N;        /* product [M x K] . [K x N] -> [M x N], complex */
-  double flops;           /* 8 M K N */
-  double bytes;           /* 8 (M K + M N + K N): one read of stem and branch, one write */
+  int64_t M, K, N;        /* product [M x K] . [K x N] -> [M x N], complex, per batch index */
+  double flops;           /* 8 M K N 2^n_batch */
+  double bytes;           /* 8 (M K + M N + K N) 2^n_batch: one read of stem and branch, one write */
   double perm_bytes;      /* 16 * 2^rank_in if permuted, else 0 */
   float last_gemm_us;     /* product launch of the last STEM_TIME_STEPS call, or -1;
                              one launch covers last_slices slices */
@@ -118,6 +122,9 @@ typedef struct stem_step_info {
   int32_t sched_lds;      /* branch in LDS: 1, 0, or -1 = when it fits */
   float tuned_us;         /* stem_tune's time of that schedule per launch, or -1 */
   int32_t tuned_slices;   /* slices per launch stem_tune measured with */
+  int32_t n_batch;        /* labels the stem and the branch share and keep (a later branch
+                             or the result carries them): the product is batched over their
+                             2^n_batch values, each with its own branch sub-matrix */
 } stem_step_info;
 
 /* Summary of a plan, computed on the host without a GPU. */

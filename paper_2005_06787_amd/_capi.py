@@ -61,6 +61,7 @@ class stem_step_info(ctypes.Structure):
         ("sched_tm", ctypes.c_int32), ("sched_ntw", ctypes.c_int32),
         ("sched_blocks", ctypes.c_int32), ("sched_lds", ctypes.c_int32),
         ("tuned_us", ctypes.c_float), ("tuned_slices", ctypes.c_int32),
+        ("n_batch", ctypes.c_int32),
     ]
 
 

@@ -71,6 +71,22 @@ static Operand plain_operand(const void* ptr, int64_t zstride) {
   return o;
 }
 
+// The product operands of a step with h batch labels: launch item z is
+// slice z >> h, batch index z & (2^h - 1), whose bits sit at the address
+// positions pos (stem and output; none for the branch, whose variant
+// selects them).
+static Operand batched(Operand o, int h, const int32_t* pos) {
+  o.hbits = h;
+  o.nhpos = pos ? h : 0;
+  for (int q = 0; q < h && pos; ++q) o.hpos[q] = (int8_t)pos[q];
+  return o;
+}
+
+static void out_batch_pos(const StepLayout& S, int32_t* pos) {
+  const int h = (int)S.batch.size();
+  for (int q = 0; q < h; ++q) pos[q] = S.rank_out - h + q;
+}
+
 // Variant selection of a tensor's fixed labels (MSB first) for one
 // projected assignment pa: projected bits go into vbase, sliced ones are
 // read from the slice id on the device.
@@ -78,9 +94,15 @@ static SliceSel make_sel(const std::vector<FixedSrc>& src, uint64_t pa, int n_sl
   SliceSel s;
   std::memset(&s, 0, sizeof(s));
   const int nf = (int)src.size();
+  int h = 0;  // the step's batch labels: batch index bit h-1-index
+  for (const FixedSrc& f : src) h += f.is_proj == 2 ? 1 : 0;
   for (int j = 0; j < nf; ++j) {
     const int vpos = nf - 1 - j;
-    if (src[j].is_proj) {
+    if (src[j].is_proj == 2) {
+      s.hshift[s.nh] = (int8_t)(h - 1 - src[j].index);
+      s.hvpos[s.nh] = (int8_t)vpos;
+      s.nh++;
+    } else if (src[j].is_proj) {
       s.vbase |= (uint64_t)fixed_bit(src[j], 0, pa, n_sliced, n_proj) << vpos;
     } else {
       s.vshift[s.nv] = (int8_t)(n_sliced - 1 - src[j].index);
@@ -281,8 +303,10 @@ static void fill_info(const StepLayout& S, stem_step_info* info) {
   info->K = S.K;
   info->N = S.N;
   const double M = (double)S.M, K = (double)S.K, N = (double)S.N;
-  info->flops = 8.0 * M * K * N;
-  info->bytes = 8.0 * (M * K + M * N + K * N);
+  const double H = (double)(1 << S.batch.size());
+  info->n_batch = (int32_t)S.batch.size();
+  info->flops = 8.0 * H * M * K * N;
+  info->bytes = 8.0 * H * (M * K + M * N + K * N);
   info->perm_bytes = S.permuted ? 16.0 * (double)(1ull << S.rank_in) : 0.0;
   info->last_gemm_us = -1.f;
   info->last_perm_us = -1.f;
@@ -428,6 +452,9 @@ stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, i
   const PlanLayout& L = p->L;
   if (L.steps.empty()) return STEM_OK;
   if (nz < 1 || nz > (uint32_t)kMaxSlicesInFlight) return fail(STEM_ERANGE, "slices_in_flight");
+  for (const StepLayout& S : L.steps)
+    if (((uint64_t)nz << S.batch.size()) > 65535u)
+      return fail(STEM_ERANGE, "slices_in_flight x 2^(batch labels of a step) above 65535");
   const uint64_t per = slice_ws_bytes(p);
   if (!ws || ws_bytes < per * nz)
     return fail(STEM_ENOMEM, "workspace smaller than stem_plan_workspace_bytes(plan, slices)");
@@ -446,8 +473,10 @@ stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, i
   stem_status rs = STEM_OK;
   for (size_t i = 0; i < L.steps.size() && rs == STEM_OK; ++i) {
     StepLayout& S = p->L.steps[i];
+    const int h = (int)S.batch.size();
+    const int nzh = (int)(nz << h);
     const TuneKey key{p->precision, S.gemm.amode, S.gemm.cmode, ilog2(S.M), ilog2(S.K),
-                      ilog2(S.N), (int)nz};
+                      ilog2(S.N), nzh};
     auto it = best.find(key);
     if (!force && it != best.end()) {
       S.sched = it->second.sched;
@@ -455,13 +484,17 @@ stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, i
       p->tuned_nz[i] = (int)nz;
       continue;
     }
-    const Operand bop = plain_operand(p->d_branch + p->sd[i].boff, 0);
+    int32_t cpos[kMaxBatchLabels];
+    out_batch_pos(S, cpos);
+    const Operand bop = batched(plain_operand(p->d_branch + p->sd[i].boff, 0), h, nullptr);
+    const Operand a_in = batched(in, h, S.hpos_a);
+    const Operand c_out = batched(out, h, cpos);
     TuneBest win;
     for (const GemmSched& c : candidates(S, p->precision)) {
-      hipError_t e = launch_cgemm(p->precision, in, bop, out, 0, (int)nz, S.M, S.K, S.N, S.gemm, c, st);
+      hipError_t e = launch_cgemm(p->precision, a_in, bop, c_out, 0, nzh, S.M, S.K, S.N, S.gemm, c, st);
       if (e == hipSuccess) e = hipEventRecord(e0, st);
       for (int r = 0; r < nrep && e == hipSuccess; ++r)
-        e = launch_cgemm(p->precision, in, bop, out, 0, (int)nz, S.M, S.K, S.N, S.gemm, c, st);
+        e = launch_cgemm(p->precision, a_in, bop, c_out, 0, nzh, S.M, S.K, S.N, S.gemm, c, st);
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -515,6 +548,11 @@ static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
                                    std::to_string(per) + " per slice in flight");
     group = std::min<uint64_t>(ws_bytes / per, kMaxSlicesInFlight);
   }
+  // a batched step launches 2^h items per slice; the grid's z extent is
+  // at most 65535
+  size_t hmax = 0;
+  for (const StepLayout& S : L.steps) hmax = std::max(hmax, S.batch.size());
+  group = std::min<uint64_t>(group, 65535u >> hmax);
   const uint64_t n_out = 1ull << L.open.size();
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -564,8 +602,13 @@ static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
         Operand bop = plain_operand(p->d_branch + p->sd[i].boff, 0);
         bop.vstride = (int64_t)p->sd[i].bstride;
         bop.sel = bsel[i];
+        const int h = (int)S.batch.size();
+        int32_t cpos[kMaxBatchLabels];
+        out_batch_pos(S, cpos);
         if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 2], st));
-        hipError_t e = launch_cgemm(p->precision, cur, bop, o, c0, nz, S.M, S.K, S.N, S.gemm, S.sched, st);
+        hipError_t e = launch_cgemm(p->precision, batched(cur, h, S.hpos_a), batched(bop, h, nullptr),
+                                    batched(o, h, cpos), c0, nz << h, S.M, S.K, S.N, S.gemm,
+                                    S.sched, st);
         if (e != hipSuccess) return fail(STEM_EHIP, std::string("product: ") + hipGetErrorString(e));
         if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 3], st));
         cur = o;

@@ -25,12 +25,20 @@ constexpr int kTargetBlocks = 4096;    // workgroups per launch before row loops
 // predicate, so every table index is a constant and the tables stay in
 // scalar registers instead of being copied into per-lane arrays.
 __device__ __forceinline__ const char* op_base(const Operand& o, int z, uint64_t s0) {
+  const uint32_t j = (uint32_t)z >> o.hbits;
+  const uint32_t hb = (uint32_t)z & ((1u << o.hbits) - 1u);
   uint64_t v = o.sel.vbase;
-  const uint64_t s = s0 + (uint64_t)z;
+  const uint64_t s = s0 + (uint64_t)j;
 #pragma unroll
-  for (int j = 0; j < kMaxSlicedPerTensor; ++j)
-    if (j < o.sel.nv) v |= ((s >> o.sel.vshift[j]) & 1ull) << o.sel.vpos[j];
-  return (const char*)o.ptr + (int64_t)z * o.zstride + (int64_t)v * o.vstride;
+  for (int q = 0; q < kMaxSlicedPerTensor; ++q)
+    if (q < o.sel.nv) v |= ((s >> o.sel.vshift[q]) & 1ull) << o.sel.vpos[q];
+  int64_t off = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxBatchLabels; ++q) {
+    if (q < o.sel.nh) v |= (uint64_t)((hb >> o.sel.hshift[q]) & 1u) << o.sel.hvpos[q];
+    if (q < o.nhpos) off |= (int64_t)((hb >> q) & 1u) << o.hpos[q];
+  }
+  return (const char*)o.ptr + (int64_t)j * o.zstride + (int64_t)v * o.vstride + 8 * off;
 }
 
 // ---------------------------------------------------------------------------
@@ -67,7 +75,7 @@ __device__ __forceinline__ int64_t row_lo(int r16, const GemmGeom& g) {
 __device__ __forceinline__ int64_t row_hi(int64_t mh, const GemmGeom& g) {
   int64_t a = mh;
 #pragma unroll
-  for (int i = 0; i < kMaxShared + 4; ++i) {
+  for (int i = 0; i < kMaxShared + 4 + kMaxBatchLabels; ++i) {
     if (i < g.nins) {
       const int p = g.ins[i];
       a = ((a >> p) << (p + 1)) | (a & ((1ll << p) - 1));
@@ -171,7 +179,7 @@ static inline GemmGeom make_geom(const GemmLayout& lay, int64_t M, int64_t K, in
   for (int i = 0; i < 16; ++i) g.spos[i] = lay.spos[i];
   for (int i = 0; i < 4; ++i) g.mlo[i] = lay.mlo[i];
   g.nins = lay.nins;
-  for (int i = 0; i < 20; ++i) g.ins[i] = lay.ins[i];
+  for (int i = 0; i < 24; ++i) g.ins[i] = lay.ins[i];
   return g;
 }
 

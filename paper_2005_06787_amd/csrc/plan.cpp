@@ -194,9 +194,8 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     }
   }
   for (int32_t x : L->open)
-    if (count[x] != 1) {
-      *err = "open label " + std::to_string(x) + " occurs in " + std::to_string(count[x]) +
-             " tensors (must be 1)";
+    if (count[x] < 1) {
+      *err = "open label " + std::to_string(x) + " occurs in no tensor";
       return STEM_ELABEL;
     }
   for (auto& kv : fixed)
@@ -206,9 +205,9 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     }
   for (auto& kv : count) {
     if (open_set.count(kv.first) || fixed.count(kv.first)) continue;
-    if (kv.second != 2) {
+    if (kv.second < 2) {
       *err = "label " + std::to_string(kv.first) + " occurs in " + std::to_string(kv.second) +
-             " tensors (a summed label must join exactly two)";
+             " tensor (a summed label must join two or more)";
       return STEM_ELABEL;
     }
   }
@@ -229,7 +228,7 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
   std::vector<int32_t> cur = L->stem_rest;
   auto too_many_fixed = [](const std::vector<FixedSrc>& src) {
     int n_sl = 0;
-    for (const FixedSrc& f : src) n_sl += f.is_proj ? 0 : 1;
+    for (const FixedSrc& f : src) n_sl += f.is_proj == 0 ? 1 : 0;
     return n_sl > kMaxSlicedPerTensor || src.size() > 62;
   };
   if (too_many_fixed(L->stem_fixed_src)) {
@@ -284,22 +283,38 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
         rest_b.push_back(x);
       }
     }
+    std::set<int32_t> rest_set(rest_b.begin(), rest_b.end());
+    std::set<int32_t> cur_set(cur.begin(), cur.end());
+    // labels the stem and the branch share: summed, or kept when a later
+    // branch or the result still carries them (batch labels: the product
+    // runs once per assignment of them, a batched product)
+    std::vector<int32_t> shared, keep;
+    for (int32_t x : cur) {
+      if (!rest_set.count(x))
+        keep.push_back(x);
+      else if (later[i].count(x) || open_set.count(x))
+        st.batch.push_back(x);
+      else
+        shared.push_back(x);
+    }
+    for (int32_t x : rest_b)
+      if (!cur_set.count(x)) st.free_labels.push_back(x);
+    const int h = (int)st.batch.size();
+    if (h > kMaxBatchLabels) {
+      *err = "step " + std::to_string(i) + " keeps " + std::to_string(h) +
+             " labels shared by the stem and the branch (at most 4)";
+      return STEM_EUNSUPPORTED;
+    }
+    // the branch's batch labels select its variant like fixed labels do
+    for (int j = 0; j < h; ++j) {
+      st.fixed.push_back(st.batch[j]);
+      st.fixed_src.push_back(FixedSrc{2, j});
+    }
     if (too_many_fixed(st.fixed_src)) {
       *err = "branch " + std::to_string(i) + " carries more than 32 sliced labels";
       return STEM_EUNSUPPORTED;
     }
-    std::set<int32_t> rest_set(rest_b.begin(), rest_b.end());
-    std::set<int32_t> cur_set(cur.begin(), cur.end());
-    std::vector<int32_t> shared, keep;
-    for (int32_t x : cur) (rest_set.count(x) ? shared : keep).push_back(x);
-    for (int32_t x : rest_b)
-      if (!cur_set.count(x)) st.free_labels.push_back(x);
-    for (int32_t x : shared)
-      if (later[i].count(x) || open_set.count(x)) {
-        *err = "label " + std::to_string(x) + " shared by the stem and branch " +
-               std::to_string(i) + " is needed later (hyperedge)";
-        return STEM_EUNSUPPORTED;
-      }
+    std::set<int32_t> batch_set(st.batch.begin(), st.batch.end());
     const int R = (int)cur.size();
     const int s = (int)shared.size();
     st.rank_in = R;
@@ -316,7 +331,7 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     // labels that become the output's fastest are the input's 4 fastest in
     // M-fast mode and otherwise the 4 kept labels whose next use is latest.
     std::set<int32_t> shared_set(shared.begin(), shared.end());
-    const int m_bits = R - s;
+    const int m_bits = R - s - h;
     const int n_lo = std::min(4, m_bits);
     // Labels for the output's `count` fastest bits (bit 0 first).  Best: 3 or
     // more kept labels that a later step sums together (the latest such
@@ -350,7 +365,7 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     };
     bool bottom_kept = m_bits >= 4;
     for (int q = 0; q < 4 && bottom_kept; ++q)
-      if (shared_set.count(cur[R - 1 - q])) bottom_kept = false;
+      if (shared_set.count(cur[R - 1 - q]) || batch_set.count(cur[R - 1 - q])) bottom_kept = false;
     bool low_summed = true;
     for (int q = 0; q < std::min(s, 3); ++q)
       if (!shared_set.count(cur[R - 1 - q])) low_summed = false;
@@ -374,12 +389,14 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
         const std::set<int32_t> b4s(b4.begin(), b4.end());
         for (int32_t x : keep)
           if (!b4s.count(x)) st.labels_gemm.push_back(x);
+        st.labels_gemm.insert(st.labels_gemm.end(), st.batch.begin(), st.batch.end());
         st.labels_gemm.insert(st.labels_gemm.end(), shared.begin(), shared.end());
         for (int q = 3; q >= 0; --q) st.labels_gemm.push_back(b4[q]);
         mlo_labels = b4;
         G.amode = 1;
       } else {
         st.labels_gemm = keep;
+        st.labels_gemm.insert(st.labels_gemm.end(), st.batch.begin(), st.batch.end());
         st.labels_gemm.insert(st.labels_gemm.end(), shared.begin(), shared.end());
         mlo_labels = latest(keep, n_lo);
         G.amode = 0;
@@ -395,13 +412,21 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     // so k's low bits are its fastest summed labels
     std::vector<int32_t> kept_g;
     st.sigma.clear();
-    for (int32_t x : st.labels_gemm) (shared_set.count(x) ? st.sigma : kept_g).push_back(x);
+    for (int32_t x : st.labels_gemm) {
+      if (shared_set.count(x))
+        st.sigma.push_back(x);
+      else if (!batch_set.count(x))
+        kept_g.push_back(x);
+    }
+    // batch index bit q (q = 0 least significant) is batch label h-1-q
+    for (int q = 0; q < h; ++q) st.hpos_a[q] = pos_of(st.batch[h - 1 - q]);
     G.s = s;
     G.f = st.f;
     for (int j = 0; j < s; ++j) G.spos[s - 1 - j] = pos_of(st.sigma[j]);
     // m index: bits 0..3 at the chosen labels, the rest in address order
     std::vector<int32_t> ins;
     for (int j = 0; j < s; ++j) ins.push_back(G.spos[j]);
+    for (int q = 0; q < h; ++q) ins.push_back(st.hpos_a[q]);
     const std::set<int32_t> mlo_set(mlo_labels.begin(), mlo_labels.end());
     for (int b = 0; b < (int)mlo_labels.size(); ++b) {
       G.mlo[b] = pos_of(mlo_labels[b]);
@@ -414,7 +439,10 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     for (int32_t x : kept_g)
       if (!mlo_set.count(x)) m_hi.push_back(x);
     G.cmode = m_bits >= 4 ? 1 : 0;
-    st.labels_after = m_hi;
+    // the output: batch labels most significant, then the product's rows
+    // and columns
+    st.labels_after = st.batch;
+    st.labels_after.insert(st.labels_after.end(), m_hi.begin(), m_hi.end());
     if (G.cmode == 1)
       st.labels_after.insert(st.labels_after.end(), st.free_labels.begin(), st.free_labels.end());
     for (int b = (int)mlo_labels.size() - 1; b >= 0; --b) st.labels_after.push_back(mlo_labels[b]);
@@ -426,14 +454,14 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
              " above max_rank " + std::to_string(L->max_rank);
       return STEM_ESHAPE;
     }
-    st.M = 1ll << (R - s);
+    st.M = 1ll << (R - s - h);
     st.K = 1ll << s;
     st.N = 1ll << st.f;
     L->peak_rank = std::max(L->peak_rank, st.rank_out);
     L->max_ws_rank = std::max(L->max_ws_rank, st.rank_out);
-    const double M = (double)st.M, K = (double)st.K, N = (double)st.N;
-    S.flops_per_slice += 8.0 * M * K * N;
-    S.bytes_per_slice += 8.0 * (M * K + M * N + K * N);
+    const double M = (double)st.M, K = (double)st.K, N = (double)st.N, H = (double)(1 << h);
+    S.flops_per_slice += 8.0 * H * M * K * N;
+    S.bytes_per_slice += 8.0 * H * (M * K + M * N + K * N);
     if (st.permuted) {
       S.perm_bytes_per_slice += 16.0 * (double)(1ull << R);
       S.n_permutes++;

@@ -56,8 +56,8 @@ struct GemmLayout {
   int32_t amode, cmode, s, f;
   int32_t spos[16];     // stem address position of k bit i (i = 0 least significant)
   int32_t mlo[4];       // address positions of m bits 0..3
-  int32_t nins;         // positions to skip when spreading m >> 4 (summed + mlo)
-  int32_t ins[20];      // ascending
+  int32_t nins;         // positions to skip when spreading m >> 4 (summed, mlo, batch)
+  int32_t ins[24];      // ascending
 };
 
 // Launch schedule of one product (chosen by the autotuner; 0 = default):
@@ -76,10 +76,11 @@ struct GemmGeom {
   int32_t spos[16];
   int32_t mlo[4];
   int32_t nins;
-  int32_t ins[20];
+  int32_t ins[24];
 };
 
 constexpr int kMaxShared = 16;  // K <= 2^16
+constexpr int kMaxBatchLabels = 4;  // labels shared by stem and branch and kept, per step
 constexpr int kMaxFree = 16;    // N <= 2^16
 constexpr int kMaxSlicedPerTensor = 32;
 constexpr int kMaxSlicesInFlight = 4096;
@@ -88,28 +89,39 @@ constexpr int kBranchHeader = 256;  // bytes before each branch variant's fragme
 // Selection of one slice's sub-tensor: the variant index (the values of the
 // tensor's fixed labels, most significant first) is vbase (bits fixed by
 // the projected assignment) plus, for each sliced label j, bit vshift[j] of
-// the slice id placed at variant bit vpos[j].
+// the slice id placed at variant bit vpos[j], plus, for each batch label i
+// of the step, bit hshift[i] of the batch index placed at variant bit
+// hvpos[i].
 struct SliceSel {
   uint64_t vbase;
   int32_t nv;
-  int32_t pad;
+  int32_t nh;
   int8_t vshift[kMaxSlicedPerTensor];
   int8_t vpos[kMaxSlicedPerTensor];
+  int8_t hshift[kMaxBatchLabels];
+  int8_t hvpos[kMaxBatchLabels];
 };
 
-// A kernel operand for a batch of slices: batch item z (slice s0 + z)
-// starts at ptr + z * zstride + variant(s0 + z) * vstride (bytes).
+// A kernel operand for a batch of slices.  A launch's batch item z is
+// slice s0 + (z >> hbits) of the group and batch index hb = z & (2^hbits -
+// 1) over the step's batch labels (labels the stem and the branch share
+// and keep, a batched product); it starts at ptr + (z >> hbits) * zstride
+// + variant * vstride + 8 * (sum_i bit i of hb << hpos[i]) bytes.
 struct Operand {
   const void* ptr;
   int64_t zstride;
   int64_t vstride;
   SliceSel sel;
+  int32_t hbits;
+  int32_t nhpos;
+  int8_t hpos[kMaxBatchLabels];
+  int32_t pad;
 };
 
 // Where the value of a fixed (sliced or projected) label comes from.
 struct FixedSrc {
-  int32_t is_proj;      // 0: sliced label, 1: projected label
-  int32_t index;        // position in sliced_labels / proj_labels
+  int32_t is_proj;      // 0: sliced label, 1: projected label, 2: batch label of the step
+  int32_t index;        // position in sliced_labels / proj_labels / the step's batch labels
 };
 
 struct StepLayout {
@@ -122,6 +134,8 @@ struct StepLayout {
   std::vector<int32_t> free_labels;    // new labels, N index order (first = MSB)
   std::vector<int32_t> fixed;          // branch labels fixed per slice/batch, MSB first
   std::vector<FixedSrc> fixed_src;
+  std::vector<int32_t> batch;          // labels shared and kept (batched product), MSB first
+  int32_t hpos_a[kMaxBatchLabels] = {0, 0, 0, 0};  // stem address bit of batch-index bit i
   int32_t branch_index = 0;
   int64_t M = 0, K = 0, N = 0;
   GemmLayout gemm{};
@@ -162,6 +176,7 @@ void host_relayout(const float* src, float* dst, const std::vector<int32_t>& fro
 
 // Value (0/1) of a fixed label for slice id s and projected assignment p.
 inline int fixed_bit(const FixedSrc& fs, uint64_t s, uint64_t p, int n_sliced, int n_proj) {
+  if (fs.is_proj == 2) return 0;  // batch labels vary within a launch (SliceSel::hshift)
   if (fs.is_proj) return (int)((p >> (n_proj - 1 - fs.index)) & 1ull);
   return (int)((s >> (n_sliced - 1 - fs.index)) & 1ull);
 }

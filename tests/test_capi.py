@@ -82,8 +82,8 @@ def test_error_codes():
     with pytest.raises(C.StemError) as e:
         stem_plan_validate(bad)
     assert e.value.status == C.STEM_ELABEL
-    bad = dict(net, branches=net["branches"] + [{"labels": [1], "data": np.ones(2)}])
-    with pytest.raises(C.StemError) as e:       # label 1 in three tensors
+    bad = dict(net, branches=[{"labels": [1, 5], "data": np.ones((2, 2))}] + net["branches"])
+    with pytest.raises(C.StemError) as e:       # label 5 in one tensor, not open
         stem_plan_validate(bad)
     assert e.value.status == C.STEM_ELABEL
     with pytest.raises(C.StemError) as e:
@@ -95,6 +95,35 @@ def test_error_codes():
     assert e.value.status == C.STEM_ELABEL
     assert C.lib().stem_plan_validate(None, None) == C.STEM_EINVAL
     assert b"null" in C.lib().stem_last_error()
+
+
+def test_hyperedge_steps_are_batched():
+    """Label 1 joins three tensors: step 0 keeps it (a batched product over
+    its 2 values), step 2 sums it."""
+    from paper_2005_06787_amd import runtime_model as rm
+
+    net = _tiny()
+    hyper = dict(net, branches=net["branches"] + [{"labels": [1], "data": np.ones(2)}])
+    s = stem_plan_validate(hyper)
+    assert s["n_steps"] == 3
+    steps = rm.plan_steps(hyper)
+    assert [st.n_batch for st in steps] == [1, 0, 0]
+    # step 0: stem [0, 1] x branch [1, 2], 1 kept: M = 2 (label 0), K = 1, N = 2
+    assert (steps[0].M, steps[0].K, steps[0].N) == (2, 1, 2)
+    assert steps[0].flops == 8.0 * 2 * (2 * 1 * 2)
+
+
+def test_too_many_batch_labels_in_one_step():
+    rng = np.random.Generator(np.random.PCG64(1))
+    d = lambda r: rng.standard_normal((2,) * r) + 0j  # noqa: E731
+    # the stem and branch 0 share 0..4, all needed again by branch 1
+    net = {"open_labels": [5], "sliced_labels": [], "proj_labels": [],
+           "stem": {"labels": [0, 1, 2, 3, 4], "data": d(5)},
+           "branches": [{"labels": [0, 1, 2, 3, 4, 5], "data": d(6)},
+                        {"labels": [0, 1, 2, 3, 4], "data": d(5)}]}
+    with pytest.raises(C.StemError) as e:
+        stem_plan_validate(net)
+    assert e.value.status == C.STEM_EUNSUPPORTED
 
 
 def test_status_strings():

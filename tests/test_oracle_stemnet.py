@@ -113,3 +113,29 @@ def test_step_rows_equals_contract_step(seed):
     idx = rng.choice(ref.size, size=20, replace=False)
     got = stemnet.step_rows(sl, lambda i: flat[i], bl, br, order, idx)
     assert np.allclose(got, ref[idx], atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hyperedge_slices_equal_bruteforce(seed):
+    """Networks where a step keeps labels it shares with the stem (a later
+    branch or the result carries them again): the stem oracle keeps them
+    as common indices and still equals the literal path sum."""
+    from workloads.networks import random_stem_network
+
+    plan = random_stem_network(300 + seed, stem_rank=5, n_steps=5, s_range=(1, 3),
+                               f_range=(0, 2), n_sliced=1, n_proj=1, batch_prob=0.6,
+                               rank_bounds=(2, 7), dtype=np.complex128)
+    counts = {}
+    for lab, _ in _all_tensors(plan):
+        for x in lab:
+            counts[x] = counts.get(x, 0) + 1
+    opened = set(plan["open_labels"])
+    assert any(c >= 3 for c in counts.values()) or any(
+        counts[x] >= 2 for x in opened), "no hyperedge drawn"
+    for p in range(1 << len(plan["proj_labels"])):
+        for s in range(1 << len(plan["sliced_labels"])):
+            assign = stemnet.slice_assignment(plan, s)
+            assign.update(stemnet.proj_assignment(plan, p))
+            ref = tn.value_bruteforce(_fixed_network(plan, assign), plan["open_labels"])
+            got, _ = stemnet.run_slice(plan, s, p)
+            assert np.allclose(got, ref, atol=1e-10)

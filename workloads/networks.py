@@ -7,8 +7,10 @@ A stem network is the plain dictionary both sides read:
      "branches": [{"labels": [...], "data": complex array}, ...]}
 
 Every label joins exactly two tensors, except open labels (one tensor),
-projected labels (a dangling leg of one tensor, fixed per batch entry) and
-sliced labels (any joining label, enumerated outside the contraction).
+projected labels (a dangling leg of one tensor, fixed per batch entry),
+sliced labels (any joining label, enumerated outside the contraction) and,
+with ``batch_prob`` > 0, hyperedges: a label a step shares with the stem
+and keeps, so that a later step or the result carries it again.
 """
 
 from __future__ import annotations
@@ -23,7 +25,8 @@ def _cgauss(rng, shape, scale):
 def random_stem_network(seed: int, stem_rank: int = 8, n_steps: int = 6, *,
                         s_range=(1, 4), f_range=(0, 4), rank_bounds=None,
                         n_sliced: int = 2, n_proj: int = 1, n_open_final: int | None = None,
-                        fastest_prob: float = 0.3, dtype=np.complex64) -> dict:
+                        fastest_prob: float = 0.3, batch_prob: float = 0.0,
+                        dtype=np.complex64) -> dict:
     """Draw a random stem network.
 
     At each step the branch shares s labels with the stem (s uniform in
@@ -34,7 +37,10 @@ def random_stem_network(seed: int, stem_rank: int = 8, n_steps: int = 6, *,
     stays roughly constant.  A projected label is a dangling leg added to a
     random tensor; sliced labels are drawn among the joining labels.  If
     ``n_open_final`` is given, closing steps (f = 0) bring the final rank to
-    at most that value.
+    at most that value.  With ``batch_prob`` > 0 each shared label of a step
+    (at most 2 per step) is kept in the stem with that probability instead
+    of being summed: a hyperedge joining the stem, this branch and a later
+    branch or the result.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     lo, hi = rank_bounds if rank_bounds is not None else (1, stem_rank + 4)
@@ -50,15 +56,22 @@ def random_stem_network(seed: int, stem_rank: int = 8, n_steps: int = 6, *,
             shared = cur[len(cur) - s:]
         else:
             shared = [cur[int(p)] for p in sorted(rng.choice(len(cur), size=s, replace=False))]
+        kept = []
+        if batch_prob > 0:
+            for x in shared:
+                if len(kept) < 2 and rng.random() < batch_prob:
+                    kept.append(x)
         new = list(range(nxt, nxt + f))
         nxt += f
         lab = shared + new
         order = rng.permutation(len(lab))
         lab = [lab[int(o)] for o in order]
-        data = _cgauss(rng, (2,) * len(lab), 1.0 / np.sqrt(2.0 ** s))
+        n_sum = len(shared) - len(kept)
+        data = _cgauss(rng, (2,) * len(lab), 1.0 / np.sqrt(2.0 ** n_sum))
         branches.append({"labels": lab, "data": data})
-        joins.extend(shared)
-        cur = [x for x in cur if x not in set(shared)] + new
+        joins.extend(x for x in shared if x not in kept)
+        gone = set(shared) - set(kept)
+        cur = [x for x in cur if x not in gone] + new
 
     for _ in range(n_steps):
         R = len(cur)
