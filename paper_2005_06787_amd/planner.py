@@ -15,6 +15,9 @@ slicing scheme (E_s, T) whose tree T is a stem (§A.1, §A.2):
    the widest stems, whose removal gives the smallest tc (ties: lowest
    label), until the width target or the sliced-label count is met.
    tc((E_s, T)) = 2^|E_s| * sum over steps of 2^|E_step \\ E_s| (§A.1).
+   Optionally the best order is sliced again with stem-focused local
+   optimisation after every pick (§A.2: every window of consecutive
+   tensors takes its best order).
 4. The first tensors of the order are pre-contracted into the initial stem
    while its rank stays small; the rest are grouped into branches of
    consecutive tensors (§A.3, branch merging), up to a branch rank limit.
@@ -111,7 +114,8 @@ def _linear_order(tlabels, owners, rng, noise=0.5):
     return order
 
 
-def greedy_slice(od: _Order, n_sliced=None, max_width=None, forbid=(), rng=None, top: int = 3):
+def greedy_slice(od: _Order, n_sliced=None, max_width=None, forbid=(), rng=None, top: int = 3,
+                 start=()):
     """Greedy slicing of a linear order (§4, §A.2 dynamic slicing).
 
     Each pick adds, among the labels of the widest stems, the one whose
@@ -131,6 +135,12 @@ def greedy_slice(od: _Order, n_sliced=None, max_width=None, forbid=(), rng=None,
     taken = np.zeros(len(od.labels), dtype=bool)
     w = od.smat.sum(axis=1)
     u = od.umat.sum(axis=1)
+    for x in start:               # labels already sliced
+        i = od.col[x]
+        taken[i] = True
+        sliced.append(x)
+        w = w - od.smat[:, i]
+        u = u - od.umat[:, i]
     while True:
         peak = int(w.max())
         if n_sliced is not None and len(sliced) >= n_sliced:
@@ -155,8 +165,98 @@ def greedy_slice(od: _Order, n_sliced=None, max_width=None, forbid=(), rng=None,
     return sorted(sliced)
 
 
-def find_scheme(tlabels, trials: int, seed: int, n_sliced=None, max_width=None, forbid=()):
-    """Best linear order + slicing over seeded trials: (order, sliced, peak, tc)."""
+def _label_masks(tlabels):
+    bit = {x: 1 << i for i, x in enumerate(sorted(set().union(*tlabels)))}
+    return [sum(bit[x] for x in t) for t in tlabels], bit
+
+
+def local_optimize(tlabels, order, sliced=(), window: int = 4, passes: int = 3):
+    """Stem-focused local optimisation (§A.2): slide a window of
+    ``window`` consecutive tensors along the order and put them in the
+    order (of all window! orders) that gives the least (peak width of the
+    whole order, time inside the window); the stems before and after a
+    window do not depend on the order within it.  Widths and times leave
+    out the sliced labels.
+    Repeats until a pass changes nothing (at most ``passes`` passes)."""
+    import itertools
+
+    masks, bit = _label_masks(tlabels)
+    slm = 0
+    for x in sliced:
+        slm |= bit.get(x, 0)
+    keep = ~slm
+    order = list(order)
+    n = len(order)
+    w = min(window, n - 1)
+    if w < 2:
+        return order
+    for _ in range(passes):
+        changed = False
+        stems = [masks[order[0]]]
+        for j in order[1:]:
+            stems.append(stems[-1] ^ masks[j])
+        widths = [(st & keep).bit_count() for st in stems]
+        suffix = widths[:] + [0]          # suffix[k] = max width of stems k..n-1
+        for k in range(n - 1, -1, -1):
+            suffix[k] = max(widths[k], suffix[k + 1])
+        prefix = 0                        # max width of stems 0..i-1 (as reordered)
+        for i in range(1, n - w + 1):
+            prefix = max(prefix, (stems[i - 1] & keep).bit_count())
+            outside = max(prefix, suffix[i + w] if i + w <= n else 0)
+            before = stems[i - 1]
+            win = tuple(order[i:i + w])
+            best_key, best = None, win
+            for perm in itertools.permutations(win):
+                st, pk, tc = before, 0, 0.0
+                for j in perm:
+                    tc += 2.0 ** ((st | masks[j]) & keep).bit_count()
+                    st ^= masks[j]
+                    pk = max(pk, (st & keep).bit_count())
+                key = (max(pk, outside), tc)
+                if best_key is None or key < best_key:
+                    best_key, best = key, perm
+            if best != win:
+                order[i:i + w] = list(best)
+                st = before
+                for k in range(i, i + w):
+                    st ^= masks[order[k]]
+                    stems[k] = st
+                changed = True
+        if not changed:
+            break
+    return order
+
+
+def refine_scheme(tlabels, order, n_sliced=None, max_width=None, forbid=(), window: int = 4):
+    """Dynamic slicing interleaved with local optimisation (§A.2): after
+    every greedy pick the order is locally re-optimised for the labels
+    sliced so far.  Returns (order, sliced, peak, tc)."""
+    order = local_optimize(tlabels, order, (), window)
+    sliced = []
+    while True:
+        od = _Order(tlabels, order)
+        peak = max(od.widths(frozenset(sliced)))
+        if n_sliced is not None and len(sliced) >= n_sliced:
+            break
+        if n_sliced is None and (max_width is None or peak <= max_width):
+            break
+        nxt = greedy_slice(od, n_sliced=len(sliced) + 1, forbid=forbid, start=sliced)
+        if len(nxt) == len(sliced):
+            break
+        sliced = nxt
+        order = local_optimize(tlabels, order, sliced, window)
+    od = _Order(tlabels, order)
+    fs = frozenset(sliced)
+    return order, sorted(sliced), max(od.widths(fs)), od.tc(fs)
+
+
+def find_scheme(tlabels, trials: int, seed: int, n_sliced=None, max_width=None, forbid=(),
+                local_window: int = 0):
+    """Best linear order + slicing over seeded trials: (order, sliced, peak, tc).
+
+    With ``local_window`` >= 2 the best trial's order is then sliced again
+    with local optimisation after every pick (``refine_scheme``), and the
+    refined scheme is kept when its (peak width, tc) is lower."""
     owners: dict = {}
     for i, lab in enumerate(tlabels):
         for x in lab:
@@ -172,6 +272,11 @@ def find_scheme(tlabels, trials: int, seed: int, n_sliced=None, max_width=None, 
         if best is None or key < best[0]:
             best = (key, order, sl)
     (peak, tc), order, sl = best
+    if local_window >= 2:
+        r = refine_scheme(tlabels, order, n_sliced=n_sliced, max_width=max_width, forbid=forbid,
+                          window=local_window)
+        if (r[2], r[3]) < (peak, tc):
+            return r
     return order, sl, peak, tc
 
 
@@ -384,7 +489,7 @@ def scheme_network(pb: CircuitProblem, order, sliced, *, init_rank: int = 12,
 def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=(), *,
                  n_sliced=None, max_width=None, trials: int = 64, seed: int = 0,
                  init_rank: int = 12, max_branch_rank: int = 12, merge: str = "dp",
-                 step_cost=None) -> dict:
+                 step_cost=None, local_window: int = 0) -> dict:
     """Sliced stem network of a circuit's amplitudes.
 
     ``open_qubits`` stay open (result index, first qubit most significant),
@@ -394,7 +499,8 @@ def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=()
     """
     pb = CircuitProblem(circuit, open_qubits, closed_bits, proj_qubits)
     order, sliced, peak, tc = find_scheme(pb.tlabels, trials, seed, n_sliced=n_sliced,
-                                          max_width=max_width, forbid=pb.forbid)
+                                          max_width=max_width, forbid=pb.forbid,
+                                          local_window=local_window)
     stats = {"peak_width": int(peak), "tc": float(tc),
              "log2_tc": float(math.log2(tc)) if tc > 0 else 0.0, "order": list(order)}
     return scheme_network(pb, order, sliced, init_rank=init_rank,

@@ -39,7 +39,8 @@ def scheme():
     pb = planner.CircuitProblem(circ, oq, closed)
     order, sliced, peak, tc = planner.find_scheme(pb.tlabels, CFG["order_trials"],
                                                   CFG["order_seed"], max_width=CFG["max_width"],
-                                                  forbid=pb.forbid)
+                                                  forbid=pb.forbid,
+                                                  local_window=CFG["local_window"])
     assert peak <= CFG["max_width"]
     net = planner.scheme_network(pb, order, sliced)
     print(f"53-qubit scheme: {len(sliced)} sliced labels, peak width {peak}, "

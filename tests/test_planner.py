@@ -187,3 +187,55 @@ def test_dp_branch_merging_is_optimal_over_all_partitions():
         if c is not None and (best is None or c < best):
             best = c
     assert got == pytest.approx(best, rel=1e-12)
+
+
+def _scheme_key(tlabels, order, sliced):
+    od = planner._Order(tlabels, order)
+    fs = frozenset(sliced)
+    return max(od.widths(fs)), od.tc(fs)
+
+
+def test_local_optimize_window_is_exhaustive_and_never_worse():
+    """A window spanning every tensor after the first finds the best of all
+    orders of those tensors (checked against brute force on 7 tensors),
+    and a smaller window never makes a scheme worse."""
+    import itertools
+
+    pb = _problem()
+    order, sliced, _, _ = planner.find_scheme(pb.tlabels, 2, 1, n_sliced=2, forbid=pb.forbid)
+    sub = list(order[:7])
+    tl = [pb.tlabels[j] for j in range(len(pb.tlabels))]
+    got = planner.local_optimize(tl, sub, sliced, window=6, passes=1)
+    best = min(_scheme_key_sub(tl, [sub[0]] + list(p), sliced)
+               for p in itertools.permutations(sub[1:]))
+    assert _scheme_key_sub(tl, got, sliced) == best
+    before = _scheme_key(pb.tlabels, order, sliced)
+    after = _scheme_key(pb.tlabels, planner.local_optimize(pb.tlabels, order, sliced, window=4),
+                        sliced)
+    assert after <= before
+
+
+def _scheme_key_sub(tlabels, order, sliced):
+    """(peak width, tc) of a partial order: stems and steps of its tensors only."""
+    stem = set(tlabels[order[0]]) - set(sliced)
+    peak, tc = len(stem), 0.0
+    for j in order[1:]:
+        t = tlabels[j] - set(sliced)
+        tc += 2.0 ** len(stem | t)
+        stem ^= t
+        peak = max(peak, len(stem))
+    return peak, tc
+
+
+def test_refined_scheme_meets_the_target_and_is_no_worse():
+    pb = _problem()
+    order, sliced, peak, tc = planner.find_scheme(pb.tlabels, 4, 0, max_width=9, forbid=pb.forbid)
+    r_order, r_sliced, r_peak, r_tc = planner.refine_scheme(pb.tlabels, order, max_width=9,
+                                                            forbid=pb.forbid)
+    assert r_peak <= 9
+    assert sorted(r_order) == sorted(order)
+    assert not set(r_sliced) & pb.forbid
+    assert (r_peak, r_tc) == _scheme_key(pb.tlabels, r_order, r_sliced)
+    o2, s2, p2, tc2 = planner.find_scheme(pb.tlabels, 4, 0, max_width=9, forbid=pb.forbid,
+                                          local_window=4)
+    assert (p2, tc2) <= (peak, tc)

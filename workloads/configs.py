@@ -24,11 +24,12 @@ CIRCUIT_CONFIGS = {
 # 53 qubits (6x9 grid without site (0, 4)), 20 cycles: one slice at the
 # full per-slice width, and candidate slicing sets for the runtime models.
 # Planner: linear stem order over order_trials seeded trials, greedy slicing
-# to max_width; candidates from the randomised greedy slicer (uniform among
-# the 3 best picks) with candidate_seed.
+# to max_width, then slicing again with local optimisation over windows of
+# local_window tensors; candidates from the randomised greedy slicer
+# (uniform among the 3 best picks) with candidate_seed.
 C5_53Q_M20 = dict(rows=6, cols=9, cycles=20, seed=5, dead=((0, 4),),
                   open_rows=range(0, 2), open_cols=range(6, 9), prefix_seed=1005,
-                  max_width=30, order_trials=256, order_seed=0,
+                  max_width=30, order_trials=256, order_seed=0, local_window=4,
                   candidate_seed=5000, n_candidates=1000)
 
 # Eight 40-qubit circuits (5x8 grid) of uneven width run as one batch: the
