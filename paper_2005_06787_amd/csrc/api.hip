@@ -487,14 +487,19 @@ stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, i
     int32_t cpos[kMaxBatchLabels];
     out_batch_pos(S, cpos);
     const Operand bop = batched(plain_operand(p->d_branch + p->sd[i].boff, 0), h, nullptr);
-    const Operand a_in = batched(in, h, S.hpos_a);
-    const Operand c_out = batched(out, h, cpos);
+    // successive launches swap the two stem buffers, so that every launch
+    // reads what the one before it wrote, as the steps of a contraction do
+    // (values are irrelevant to the timing)
+    const Operand a_in[2] = {batched(in, h, S.hpos_a), batched(out, h, S.hpos_a)};
+    const Operand c_out[2] = {batched(out, h, cpos), batched(in, h, cpos)};
     TuneBest win;
     for (const GemmSched& c : candidates(S, p->precision)) {
-      hipError_t e = launch_cgemm(p->precision, a_in, bop, c_out, 0, nzh, S.M, S.K, S.N, S.gemm, c, st);
+      hipError_t e = launch_cgemm(p->precision, a_in[0], bop, c_out[0], 0, nzh, S.M, S.K, S.N,
+                                  S.gemm, c, st);
       if (e == hipSuccess) e = hipEventRecord(e0, st);
       for (int r = 0; r < nrep && e == hipSuccess; ++r)
-        e = launch_cgemm(p->precision, a_in, bop, c_out, 0, nzh, S.M, S.K, S.N, S.gemm, c, st);
+        e = launch_cgemm(p->precision, a_in[(r + 1) & 1], bop, c_out[(r + 1) & 1], 0, nzh, S.M,
+                         S.K, S.N, S.gemm, c, st);
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
