@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+FP32_PEAK_FLOPS = 157.3e12   # MI355X dense FP32 (MFMA)
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of the FP32 product kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (scaled by a 1 GiB copy), recorded with a hash of the
@@ -324,6 +325,9 @@ def roofline(plan):
     p_us = sum(s["last_perm_us"] for s in steps if s["permuted"])
     launches = len(steps)
     achieved = g_bytes / (g_us * 1e-6) / 1e9
+    # every launch on its own roofline: max(bytes / 8 TB/s, flops / 157.3 TFLOP/s)
+    roof_us = sum(max(nz * s["bytes"] / (HBM_PEAK_GBS * 1e9), nz * s["flops"] / FP32_PEAK_FLOPS)
+                  for s in steps) * 1e6
     return {
         "kernel": "stem_cgemm_f32_kernel",
         "bound": "hbm",
@@ -336,6 +340,10 @@ def roofline(plan):
         "bytes_per_launch": g_bytes / launches,
         "avg_launch_us": g_us / launches,
         "product_tflops": round(g_flops / (g_us * 1e-6) / 1e12, 3),
+        "stepwise": {"roofline_us": round(roof_us, 1), "measured_us": round(g_us, 1),
+                     "frac": round(roof_us / g_us, 4),
+                     "note": "sum over the launches of max(bytes / 8 TB/s, flops / 157.3 "
+                             "TFLOP/s), datasheet peaks, over their measured sum"},
         "permute": {"achieved_gbs": round(p_bytes / (p_us * 1e-6) / 1e9, 1) if p_us > 0 else None,
                     "bytes_per_group": p_bytes, "us_per_group": p_us},
     }
