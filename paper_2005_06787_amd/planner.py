@@ -280,6 +280,23 @@ def find_scheme(tlabels, trials: int, seed: int, n_sliced=None, max_width=None, 
     return order, sl, peak, tc
 
 
+def candidate_orders(tlabels, n: int, seed: int, n_sliced=None, max_width=None, forbid=()):
+    """n (order, sliced labels) schemes from seeded trials of the linear
+    stem search, each order sliced greedily: candidate stem orders."""
+    owners: dict = {}
+    for i, lab in enumerate(tlabels):
+        for x in lab:
+            owners.setdefault(x, []).append(i)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n):
+        order = _linear_order(tlabels, owners, rng)
+        sl = greedy_slice(_Order(tlabels, order), n_sliced=n_sliced, max_width=max_width,
+                          forbid=forbid)
+        out.append((order, sl))
+    return out
+
+
 def candidate_slicings(tlabels, order, n: int, seed: int, n_sliced=None, max_width=None,
                        forbid=(), top: int = 3):
     """n slicing sets of one order from the randomised greedy slicer

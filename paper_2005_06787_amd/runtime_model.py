@@ -24,14 +24,8 @@ N_FEATURES = C.STEM_N_FEATURES
 
 def plan_steps(net: dict, precision: str = "fp32") -> list:
     """Step infos (ctypes structs) of a network, on the host."""
-    # the step shapes depend on the labels only: absent data is zeros
-    if "data" not in net["stem"]:
-        net = dict(net, stem=dict(net["stem"], data=np.zeros(1 << len(net["stem"]["labels"]))))
-    if any("data" not in b for b in net.get("branches", [])):
-        net = dict(net, branches=[b if "data" in b else
-                                  dict(b, data=np.zeros(1 << len(b["labels"]), np.complex64))
-                                  for b in net["branches"]])
-    d = _Desc(net, precision)
+    # the step shapes depend on the labels only
+    d = _Desc(net, precision, shapes_only=True)
     n = ctypes.c_int32()
     C.check(C.lib().stem_plan_steps(ctypes.byref(d.desc), None, 0, ctypes.byref(n)))
     arr = (C.stem_step_info * max(1, n.value))()

@@ -45,7 +45,7 @@ class _Desc:
     """stem_plan_desc plus the host arrays it points into (kept alive)."""
 
     def __init__(self, net: dict, precision: str = "fp32", stem_device_ptr: int | None = None,
-                 max_rank: int = 0):
+                 max_rank: int = 0, shapes_only: bool = False):
         if precision not in C.PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(C.PRECISIONS)}")
         self.open = _i32(net.get("open_labels", []))
@@ -57,8 +57,13 @@ class _Desc:
         self.blabels = _i32(x for b in branches for x in b["labels"])
         if not len(self.blabels):
             self.blabels = np.zeros(1, dtype=np.int32)
-        self.bdata = (np.concatenate([_c64(b["data"]) for b in branches])
-                      if branches else np.zeros(1, dtype=np.complex64))
+        if shapes_only:
+            # stem_plan_validate / stem_plan_steps read labels only; the data
+            # pointers must just be non-null
+            self.bdata = np.zeros(1, dtype=np.complex64)
+        else:
+            self.bdata = (np.concatenate([_c64(b["data"]) for b in branches])
+                          if branches else np.zeros(1, dtype=np.complex64))
         d = C.stem_plan_desc()
         d.n_open, d.open_labels = len(self.open), _ptr(self.open, ctypes.c_int32)
         d.n_sliced, d.sliced_labels = len(self.sliced), _ptr(self.sliced, ctypes.c_int32)
@@ -67,6 +72,10 @@ class _Desc:
         if stem_device_ptr is not None:
             d.stem_data = ctypes.c_void_p(int(stem_device_ptr))
             d.stem_on_device = 1
+        elif shapes_only:
+            self.stem = np.zeros(1, dtype=np.complex64)
+            d.stem_data = ctypes.c_void_p(self.stem.ctypes.data)
+            d.stem_on_device = 0
         else:
             self.stem = _c64(net["stem"]["data"])
             if self.stem.size != 1 << len(self.stem_labels):
@@ -83,10 +92,9 @@ class _Desc:
 
 
 def stem_plan_validate(net: dict, precision: str = "fp32", max_rank: int = 0) -> dict:
-    """Host-only check of a stem network; returns the plan summary."""
-    if "data" not in net["stem"]:
-        net = dict(net, stem=dict(net["stem"], data=np.zeros(1 << len(net["stem"]["labels"]))))
-    d = _Desc(net, precision, max_rank=max_rank)
+    """Host-only check of a stem network (labels only; data may be absent);
+    returns the plan summary."""
+    d = _Desc(net, precision, max_rank=max_rank, shapes_only=True)
     s = C.stem_plan_summary()
     C.check(C.lib().stem_plan_validate(ctypes.byref(d.desc), ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in s._fields_}

@@ -7,9 +7,11 @@ and the ranking of candidate slicing sets by the runtime models.
   formula on the same input (the local error of each step); the last
   step's 64 values equal the whole plan's slice 0.  FP32 and split FP16,
   bound 1e-5 relative L2 per step.
-* Candidate slicing sets from the randomised greedy slicer: the analytic
-  and MLP models predict every candidate's total time (per-slice time x
-  2^|E_s|, paper §A.1); six candidates spread over the analytic ranking
+* Candidate schemes: slicing sets of the chosen order from the randomised
+  greedy slicer, and 32 other stem orders (seeded trials of the linear
+  stem search, sliced greedily).  The analytic and MLP models predict
+  every candidate's total time (per-slice time x 2^|E_s|, paper §A.1); six
+  candidates spread over the analytic ranking
   are measured (slice 0, tuned schedules), both models must order them like
   the measurements (Spearman rank correlation), and the MLP, trained on the
   scheme's own measured steps, must predict the measured times more closely
@@ -28,6 +30,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2005_06787_amd import Plan, planner  # noqa: E402
+from paper_2005_06787_amd import _capi as C  # noqa: E402
 from paper_2005_06787_amd import runtime_model as rm  # noqa: E402
 
 CFG = configs.C5_53Q_M20
@@ -111,12 +114,25 @@ def test_slice0_full_width_local_error_per_step(scheme, precision):
 def test_runtime_models_rank_candidate_slicings(scheme, tmp_path):
     pb, order, sliced, net = scheme
     log = str(tmp_path / "tune.txt")
-    cands = planner.candidate_slicings(pb.tlabels, order, CFG["n_candidates"],
-                                       CFG["candidate_seed"], max_width=CFG["max_width"],
-                                       forbid=pb.forbid)
-    assert len(cands) >= 100
-    shapes = [planner.scheme_network(pb, order, c, with_data=False) for c in cands]
-    analytic = np.array([rm.scheme_seconds(n, "fp32", 1)["analytic_total_s"] for n in shapes])
+    sets = planner.candidate_slicings(pb.tlabels, order, CFG["n_candidates"],
+                                      CFG["candidate_seed"], max_width=CFG["max_width"],
+                                      forbid=pb.forbid)
+    assert len(sets) >= 100
+    # candidate slicing sets of the chosen order, and candidate stem orders
+    others = planner.candidate_orders(pb.tlabels, 32, CFG["candidate_seed"] + 1,
+                                      max_width=CFG["max_width"], forbid=pb.forbid)
+    cands, shapes, analytic = [], [], []
+    for o, c in [(order, c) for c in sets] + others:
+        net_c = planner.scheme_network(pb, o, c, with_data=False)
+        try:   # schemes the library cannot hold (too many sliced labels on a tensor) drop out
+            t = rm.scheme_seconds(net_c, "fp32", 1)["analytic_total_s"]
+        except C.StemError:
+            continue
+        cands.append((o, c))
+        shapes.append(net_c)
+        analytic.append(t)
+    analytic = np.array(analytic)
+    assert len(cands) > len(sets)
 
     # measured step times of the scheme itself train the MLP
     base = Plan(net)
@@ -130,7 +146,7 @@ def test_runtime_models_rank_candidate_slicings(scheme, tmp_path):
     picks = [int(ranked[int(round(q * (len(ranked) - 1)))]) for q in np.linspace(0, 1, 6)]
     measured = []
     for j in picks:
-        plan = Plan(planner.scheme_network(pb, order, cands[j]))
+        plan = Plan(planner.scheme_network(pb, cands[j][0], cands[j][1]))
         plan.tune(slices_in_flight=1, reps=1, cache_path=log)
         plan.contract(0, 1)
         torch.cuda.synchronize()
@@ -140,13 +156,13 @@ def test_runtime_models_rank_candidate_slicings(scheme, tmp_path):
         plan.contract(0, 1)
         b.record()
         b.synchronize()
-        measured.append(a.elapsed_time(b) * 1e-3 * 2.0 ** len(cands[j]))
+        measured.append(a.elapsed_time(b) * 1e-3 * 2.0 ** len(cands[j][1]))
         plan.close()
     measured = np.array(measured)
     rho_an = rm.spearman(analytic[picks], measured)
     rho_mlp = rm.spearman(mlp[picks], measured)
     for j, m in zip(picks, measured):
-        print(f"candidate {j}: |E_s| {len(cands[j])}, log2 s: analytic {np.log2(analytic[j]):.2f}, "
+        print(f"candidate {j}: |E_s| {len(cands[j][1])}, log2 s: analytic {np.log2(analytic[j]):.2f}, "
               f"MLP {np.log2(mlp[j]):.2f}, measured {np.log2(m):.2f}")
     err_an = np.median(np.abs(np.log2(analytic[picks] / measured)))
     err_mlp = np.median(np.abs(np.log2(mlp[picks] / measured)))
