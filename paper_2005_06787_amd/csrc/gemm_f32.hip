@@ -59,10 +59,26 @@ __device__ __forceinline__ void f32_rows(const float* __restrict__ A,
       dst[t] = load_kr4<AM, FULL>(A, rb[t], kc * 16 + grp * 4, kh | kl0, kh | kl1, g);
   };
 
+  auto load_b = [&](float (&dst)[NTW][4], int kc) {
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) {
+      if (n < ntw) {
+        const float* bp = BLDS ? Bsrc + (kc * NTW + n) * 256 + lane
+                               : Bsrc + ((size_t)(kc * g.NT + nt0 + n) * 4) * 64 + lane;
+        dst[n][0] = bp[0];
+        dst[n][1] = bp[64];
+        dst[n][2] = bp[128];
+        dst[n][3] = bp[192];
+      }
+    }
+  };
+
   int64_t blk = blockIdx.x;
   if ((blk * 4 + wave) * (16 * TM) >= g.M) return;  // no barrier follows
   int64_t rb[TM];
   block_rows(blk, rb);
+  float bq[2][NTW][4];
+  if (R >= 2) load_b(bq[0], 0);
   f32x4 buf[R][TM];
   int64_t kh = 0;  // k offset of the chunk loaded last
 #pragma unroll
@@ -89,20 +105,22 @@ __device__ __forceinline__ void f32_rows(const float* __restrict__ A,
       const bool tail = kc + R >= g.KC;  // refills come from the next row block
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        // all branch fragments of the chunk first, then the MFMAs ordered so
-        // that TM * NTW independent accumulators separate two dependent ones
+        // the branch fragments of the chunk: prefetched one chunk ahead into
+        // the other half of bq when the ring holds an even number of chunks
+        // (chunk parity = i parity), else loaded here
         float b[NTW][4];
+        if (R >= 2) {
+          const int nk = (kc + i + 1) & (g.KC - 1);
 #pragma unroll
-        for (int n = 0; n < NTW; ++n) {
-          if (n < ntw) {
-            const float* bp = BLDS ? Bsrc + ((kc + i) * NTW + n) * 256 + lane
-                                   : Bsrc + ((size_t)((kc + i) * g.NT + nt0 + n) * 4) * 64 + lane;
-            b[n][0] = bp[0];
-            b[n][1] = bp[64];
-            b[n][2] = bp[128];
-            b[n][3] = bp[192];
-          }
+          for (int n = 0; n < NTW; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[n][q] = bq[i & 1][n][q];
+          load_b(bq[(i + 1) & 1], nk);
+        } else {
+          load_b(b, kc + i);
         }
+        // the MFMAs ordered so that TM * NTW independent accumulators
+        // separate two dependent ones
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
