@@ -14,6 +14,7 @@
 #include <tuple>
 #include <vector>
 
+#include "device_common.h"
 #include "kernels.h"
 #include "stem_internal.h"
 
@@ -428,8 +429,9 @@ std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
     for (int w : ntws)
       for (int blocks : {1024, 4096, 16384}) {
         const size_t lds = precision == STEM_FP32 ? (size_t)kc * w * 1024 : (size_t)kc * w * 2048;
-        for (int l : {-1, 0}) {
-          if (l == 0 && lds > 64 * 1024) continue;  // already global
+        for (int l : {-1, 0, 1}) {
+          if (l == 0 && lds > (size_t)kLdsBudget) continue;  // -1 is already global
+          if (l == 1 && (lds <= (size_t)kLdsBudget || lds > lds_limit())) continue;
           GemmSched s;
           s.tm = tm;
           s.ntw = w;

@@ -18,7 +18,41 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kLdsBudget = 64 * 1024;  // branch fragments staged in LDS up to this size
+constexpr int kLdsBudget = 64 * 1024;  // LDS staging by default: two workgroups still fit a CU
+constexpr int kLdsMax = 160 * 1024;    // gfx950's LDS per workgroup (schedule lds = 1)
+
+// The LDS one workgroup may use on the current device (cached per device).
+static inline size_t lds_limit() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kLdsBudget;
+  if (!cache[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = kLdsBudget;
+    cache[dev] = std::max(kLdsBudget, std::min(v, kLdsMax));
+  }
+  return (size_t)cache[dev];
+}
+
+// Whether a product stages its branch fragments (lds bytes) in LDS: the
+// schedule's choice (1 = up to the device limit, 0 = never, -1 = up to the
+// default budget).
+static inline bool use_lds(int sched_lds, size_t lds) {
+  if (sched_lds == 0) return false;
+  return lds <= (sched_lds == 1 ? lds_limit() : (size_t)kLdsBudget);
+}
+
+// Raise a kernel's dynamic LDS limit above the default when a launch needs
+// it (once per kernel and size).
+template <typename F>
+static inline hipError_t allow_lds(F* kernel, size_t lds, size_t* allowed) {
+  if (lds <= (size_t)kLdsBudget || lds <= *allowed) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) *allowed = lds;
+  return e;
+}
 constexpr int kTargetBlocks = 4096;    // workgroups per launch before row loops kick in
 
 // Loops over the small per-launch tables below are fully unrolled with a

@@ -194,7 +194,9 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32_kernel(Operand Ao, Operand
 template <int TM, int NTW, int AM, int CM, int FULL>
 static void launch_f32_f(const LaunchCtx& c, const dim3& grid) {
   const size_t lds = (size_t)c.g.KC * NTW * 256 * 4;
-  if (lds <= (size_t)kLdsBudget && c.sch.lds != 0)
+  static size_t allowed = 0;
+  if (use_lds(c.sch.lds, lds) &&
+      allow_lds(stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1, FULL>, lds, &allowed) == hipSuccess)
     hipLaunchKernelGGL((stem_cgemm_f32_kernel<TM, NTW, AM, CM, 1, FULL>), grid, dim3(256), lds,
                        c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else

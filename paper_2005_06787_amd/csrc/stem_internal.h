@@ -67,7 +67,7 @@ struct GemmSched {
   int32_t tm = 0;       // 1, 2 or 4
   int32_t ntw = 0;      // 1, 2, 4 or 8
   int32_t blocks = 0;   // 256 .. 65536
-  int32_t lds = -1;     // 1 LDS, 0 global, -1 when it fits
+  int32_t lds = -1;     // branch in LDS: 1 up to the device's 160 KB, 0 never, -1 up to 64 KB
 };
 
 struct GemmGeom {
