@@ -134,3 +134,24 @@ def test_c2_sampled_slices(c2_plan, precision):
         print("slice", s, precision, "rel L2", err, flush=True)
         assert err <= 1e-5
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_fp16"])
+def test_c2_full_size_in_the_bench_launch_configuration(c2_plan, precision, tmp_path):
+    """All 2^10 slices in the launch configuration bench.py times (its
+    slices per launch, tuned schedules) equal, bit for bit, the same slices
+    contracted one per launch and added in slice order; sampled single
+    slices match the oracle (test_c2_sampled_slices), so the full-size sum
+    does too."""
+    plan = Plan(c2_plan, precision=precision)
+    n = int(plan.summary()["n_slices"])
+    group = plan.default_slices_in_flight(n)
+    plan.tune(slices_in_flight=group, reps=1, cache_path=str(tmp_path / "tune.txt"))
+    full = plan.contract(0, n, slices_in_flight=group)
+    one = torch.zeros_like(full)
+    for s in range(n):
+        plan.contract(s, s + 1, out=one, accumulate=True, slices_in_flight=1)
+    torch.cuda.synchronize()
+    print(precision, "slices per launch", group, flush=True)
+    assert torch.equal(full, one)
+    plan.close()
