@@ -66,7 +66,9 @@ enum {
  *
  * Label rules checked by stem_plan_validate / stem_plan_create:
  *  - an open label occurs in at least one tensor;
- *  - a sliced or projected label occurs in at least one tensor and is not open;
+ *  - a sliced or projected label is not open; it may occur in no tensor (the
+ *    two halves of a join list the same ones): then every slice's value is
+ *    independent of its bit;
  *  - every other label occurs in at least two tensors (more than two: a
  *    hyperedge, §A.1);
  *  - a step keeps at most 4 of the labels the stem shares with its branch
@@ -238,6 +240,39 @@ stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_
                               stem_batch_t* batch);
 stem_status stem_batch_launch(stem_batch_t batch, void* stream);
 stem_status stem_batch_destroy(stem_batch_t batch);
+
+/*
+ * Two-sided stems (paper §A.2: a contraction tree whose root joins two
+ * stems).  The left and right plans are two stem networks over the same
+ * sliced and projected label lists (same order); for every slice id and
+ * projected assignment each is contracted as by stem_contract, and their
+ * final tensors are contracted with each other over the labels open in
+ * both (summed; complex products accumulated in FP64).  The join's open
+ * labels are the labels open in exactly one of the plans, listed in any
+ * order (open_labels, host, C order of the result, first = most
+ * significant), at most 12 of them (STEM_EUNSUPPORTED); another set is
+ * STEM_ELABEL, as are different sliced or projected lists.  The plans must
+ * live on the same device and outlive the join; they may be the same plan.
+ *
+ * stem_join_contract: out (device complex128 [n_batch][2^n_open]) receives,
+ * per projected assignment, the sum over slices [s0, s1) of the joined
+ * value, added slice by slice in slice order (STEM_ACCUMULATE adds to out;
+ * STEM_TIME_STEPS is STEM_EINVAL).  ws/ws_bytes: device workspace of at
+ * least stem_join_workspace_bytes(join, 1); the number of slices per
+ * launch is ws_bytes / that size (at most 4096), and the result does not
+ * depend on it.  Errors as for stem_contract.  A join must not be used by
+ * two calls that overlap in time, nor overlap a call on either plan.
+ */
+typedef struct stem_join_s* stem_join_t;
+
+stem_status stem_join_create(stem_plan_t left, stem_plan_t right, int32_t n_open,
+                             const int32_t* open_labels, stem_join_t* join);
+stem_status stem_join_workspace_bytes(stem_join_t join, uint32_t slices_in_flight,
+                                      uint64_t* bytes);
+stem_status stem_join_contract(stem_join_t join, uint64_t s0, uint64_t s1,
+                               const uint64_t* proj_assign, uint32_t n_batch, void* ws,
+                               uint64_t ws_bytes, double* out, uint32_t flags, void* stream);
+stem_status stem_join_destroy(stem_join_t join);
 
 /*
  * Step shapes of a descriptor, on the host without a GPU (the same layout

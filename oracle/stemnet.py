@@ -21,7 +21,8 @@ slices is the value of the unsliced network (§A.1).
 Parity pins (tests/test_oracle_stemnet.py): on tiny random stem networks the
 per-slice value equals the literal Feynman-path sum of ``network``; the sum
 over slices equals the unsliced value; the single-step row formula
-``step_rows`` equals ``contract_step`` at every row.  Plans made from
+``step_rows`` equals ``contract_step`` at every row; a slice of two stems
+joined at the root equals the path sum of the whole network.  Plans made from
 circuits are pinned against the state vector in the planner tests.
 """
 
@@ -150,6 +151,34 @@ def unsliced_value(plan: dict, proj: int = 0) -> np.ndarray:
     order = list(plan.get("open_labels", []))
     perm = [list(labels).index(x) for x in order]
     return np.transpose(arr, perm)
+
+
+def join_slice(left: dict, right: dict, open_labels, slice_id: int = 0, proj: int = 0):
+    """One slice of two stems joined at the root (paper §A.2: the root of
+    the contraction tree joins two stems).  Both halves list the same
+    sliced and projected labels; each half's slice value is taken as by
+    ``run_slice`` and the two are contracted over the labels open in both.
+    The result is ordered by ``open_labels`` (the labels open in one half).
+    """
+    vl, _ = run_slice(left, slice_id, proj)
+    vr, _ = run_slice(right, slice_id, proj)
+    lo, ro = list(left["open_labels"]), list(right["open_labels"])
+    shared = [x for x in lo if x in ro]
+    res = np.tensordot(vl, vr, axes=([lo.index(x) for x in shared], [ro.index(x) for x in shared]))
+    labels = [x for x in lo if x not in shared] + [x for x in ro if x not in shared]
+    return transpose_to(labels, res, list(open_labels))
+
+
+def join_sliced_sum(left: dict, right: dict, open_labels, slice_ids=None, proj: int = 0):
+    """Sum of ``join_slice`` over the given slice ids (default: all)."""
+    n_sl = len(left.get("sliced_labels", []))
+    if slice_ids is None:
+        slice_ids = range(1 << n_sl)
+    total = None
+    for s in slice_ids:
+        v = join_slice(left, right, open_labels, s, proj)
+        total = v.copy() if total is None else total + v
+    return total
 
 
 def transpose_to(labels, arr, order):

@@ -7,4 +7,4 @@ HIP kernels of ``_lib/libstemgpu.so`` behind the C-ABI of
 ``include/stemgpu.h``; this package marshals arguments and plans networks.
 """
 
-from .stem import Batch, Plan, stem_fill_counter, stem_plan_validate, stem_xeb_f64  # noqa: F401
+from .stem import Batch, Join, Plan, stem_fill_counter, stem_plan_validate, stem_xeb_f64  # noqa: F401

@@ -141,6 +141,16 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_void_p)]),
     "stem_batch_launch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "stem_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "stem_join_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "stem_join_workspace_bytes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32,
+                                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "stem_join_contract": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                            ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32,
+                                            ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                            ctypes.c_uint32, ctypes.c_void_p]),
+    "stem_join_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "stem_fill_counter": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.c_int32, ctypes.c_void_p]),
     "stem_xeb_f64": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,

@@ -10,6 +10,7 @@
 #include <fstream>
 #include <map>
 #include <new>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -534,6 +535,51 @@ stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, i
 }  // extern "C"
 
 // The slice loop of stem_contract; also recorded into graphs by stem_batch_create.
+// The steps of a plan for slices [c0, c0 + nz) of one projected assignment
+// (stem_op and bsel carry its variant selections): the final stems end in
+// *cur (the initial stem itself when the plan has no steps), in workspace
+// buffer *cur_buf (0 = X, 1 = Y, -1 = none).
+static stem_status run_chain(stem_plan_t p, const Operand& stem_op,
+                             const std::vector<SliceSel>& bsel, uint64_t c0, int nz,
+                             unsigned char* wsb, int64_t half, int64_t ybase, bool time_this,
+                             hipStream_t st, Operand* cur_out, int* buf_out) {
+  const PlanLayout& L = p->L;
+  Operand cur = stem_op;
+  int cur_buf = -1;
+  for (size_t i = 0; i < L.steps.size(); ++i) {
+    const StepLayout& S = L.steps[i];
+    if (S.permuted) {
+      const int dst = cur_buf == 0 ? 1 : 0;
+      const Operand o = plain_operand(wsb + (dst ? ybase : 0), half);
+      if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i], st));
+      hipError_t e = launch_permute(cur, o, S.perm, c0, nz, st);
+      if (e != hipSuccess) return fail(STEM_EHIP, std::string("permute: ") + hipGetErrorString(e));
+      if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 1], st));
+      cur = o;
+      cur_buf = dst;
+    }
+    const int dst = cur_buf == 0 ? 1 : 0;
+    const Operand o = plain_operand(wsb + (dst ? ybase : 0), half);
+    Operand bop = plain_operand(p->d_branch + p->sd[i].boff, 0);
+    bop.vstride = (int64_t)p->sd[i].bstride;
+    bop.sel = bsel[i];
+    const int h = (int)S.batch.size();
+    int32_t cpos[kMaxBatchLabels];
+    out_batch_pos(S, cpos);
+    if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 2], st));
+    hipError_t e = launch_cgemm(p->precision, batched(cur, h, S.hpos_a), batched(bop, h, nullptr),
+                                batched(o, h, cpos), c0, nz << h, S.M, S.K, S.N, S.gemm,
+                                S.sched, st);
+    if (e != hipSuccess) return fail(STEM_EHIP, std::string("product: ") + hipGetErrorString(e));
+    if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 3], st));
+    cur = o;
+    cur_buf = dst;
+  }
+  *cur_out = cur;
+  *buf_out = cur_buf;
+  return STEM_OK;
+}
+
 static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
                                  const uint64_t* proj_assign, uint32_t n_batch, void* ws,
                                  uint64_t ws_bytes, double* out, uint32_t flags, hipStream_t st) {
@@ -590,42 +636,141 @@ static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
       const int nz = (int)std::min<uint64_t>(group, s1 - c0);
       const bool time_this = timing && b + 1 == n_batch && c0 + group >= s1;
       if (time_this) p->timed_slices = nz;
-      Operand cur = stem_op;
+      Operand cur;
       int cur_buf = -1;
-      for (size_t i = 0; i < L.steps.size(); ++i) {
-        const StepLayout& S = L.steps[i];
-        if (S.permuted) {
-          const int dst = cur_buf == 0 ? 1 : 0;
-          const Operand o = plain_operand(wsb + (dst ? ybase : 0), half);
-          if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i], st));
-          hipError_t e = launch_permute(cur, o, S.perm, c0, nz, st);
-          if (e != hipSuccess) return fail(STEM_EHIP, std::string("permute: ") + hipGetErrorString(e));
-          if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 1], st));
-          cur = o;
-          cur_buf = dst;
-        }
-        const int dst = cur_buf == 0 ? 1 : 0;
-        const Operand o = plain_operand(wsb + (dst ? ybase : 0), half);
-        Operand bop = plain_operand(p->d_branch + p->sd[i].boff, 0);
-        bop.vstride = (int64_t)p->sd[i].bstride;
-        bop.sel = bsel[i];
-        const int h = (int)S.batch.size();
-        int32_t cpos[kMaxBatchLabels];
-        out_batch_pos(S, cpos);
-        if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 2], st));
-        hipError_t e = launch_cgemm(p->precision, batched(cur, h, S.hpos_a), batched(bop, h, nullptr),
-                                    batched(o, h, cpos), c0, nz << h, S.M, S.K, S.N, S.gemm,
-                                    S.sched, st);
-        if (e != hipSuccess) return fail(STEM_EHIP, std::string("product: ") + hipGetErrorString(e));
-        if (time_this) HIPCHK(hipEventRecord(p->ev[4 * i + 3], st));
-        cur = o;
-        cur_buf = dst;
-      }
+      stem_status rs = run_chain(p, stem_op, bsel, c0, nz, wsb, half, ybase, time_this, st, &cur,
+                                 &cur_buf);
+      if (rs != STEM_OK) return rs;
       hipError_t e = launch_acc_f64(cur, c0, nz, out + 2 * n_out * b, L.final_map, st);
       if (e != hipSuccess) return fail(STEM_EHIP, std::string("accumulate: ") + hipGetErrorString(e));
     }
   }
   if (timing) p->timed_pending = true;
+  return STEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Two-sided stems (paper §A.2): two plans over the same sliced and projected
+// labels, each run slice by slice, then joined at the root by contracting
+// their final tensors over the labels they share.
+// ---------------------------------------------------------------------------
+constexpr int kJoinMaxOpenLog = 12;   // the join kernel keeps 16 outputs per thread
+
+struct stem_join_s {
+  stem_plan_t left = nullptr, right = nullptr;
+  std::vector<int32_t> open;
+  std::vector<int32_t> left_order, right_order;  // [shared..., left-only...], [shared..., right-only...]
+  bool perm_left = false, perm_right = false;
+  PermArgs pl{}, pr{};
+  int a_log = 0, b_log = 0, k_log = 0, chunk_log = 0;
+  BitMap out_map{};
+  int device = 0;
+};
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Bytes per slice in flight, in the order the workspace holds them: the
+// two chains' stem buffers, the two re-ordered final tensors, the partial
+// sums of the k chunks.
+struct JoinParts {
+  uint64_t chain_l, chain_r, tl, tr, part;
+  uint64_t total() const { return chain_l + chain_r + tl + tr + part; }
+};
+
+static JoinParts join_parts(const stem_join_s* j) {
+  JoinParts q;
+  q.chain_l = slice_ws_bytes(j->left);
+  q.chain_r = slice_ws_bytes(j->right);
+  q.tl = j->perm_left ? align256(8ull << j->left->L.final_labels.size()) : 0;
+  q.tr = j->perm_right ? align256(8ull << j->right->L.final_labels.size()) : 0;
+  const uint64_t n_out = 1ull << (j->a_log + j->b_log);
+  q.part = align256((16ull * n_out) << (j->k_log - j->chunk_log));
+  return q;
+}
+
+static stem_status join_contract_impl(stem_join_s* j, uint64_t s0, uint64_t s1,
+                                      const uint64_t* proj_assign, uint32_t n_batch, void* ws,
+                                      uint64_t ws_bytes, double* out, uint32_t flags,
+                                      hipStream_t st) {
+  if (!j || !out) return fail(STEM_EINVAL, "null join or output");
+  if (flags & STEM_TIME_STEPS) return fail(STEM_EINVAL, "STEM_TIME_STEPS is not allowed on a join");
+  stem_plan_t pl = j->left, pr = j->right;
+  const int n_sl = (int)pl->L.sliced.size(), n_pr = (int)pl->L.proj.size();
+  if (s0 > s1 || s1 > (1ull << n_sl)) return fail(STEM_ERANGE, "slice range outside [0, 2^n_sliced)");
+  if (n_batch == 0) return STEM_OK;
+  if (proj_assign)
+    for (uint32_t b = 0; b < n_batch; ++b)
+      if (proj_assign[b] >= (1ull << n_pr))
+        return fail(STEM_ERANGE, "projected assignment out of range");
+  const JoinParts q = join_parts(j);
+  const uint64_t per = q.total();
+  if (!ws || ws_bytes < per)
+    return fail(STEM_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                 std::to_string(per) + " per slice in flight");
+  uint64_t group = std::min<uint64_t>(ws_bytes / per, kMaxSlicesInFlight);
+  size_t hmax = 0;
+  for (const StepLayout& S : pl->L.steps) hmax = std::max(hmax, S.batch.size());
+  for (const StepLayout& S : pr->L.steps) hmax = std::max(hmax, S.batch.size());
+  group = std::min<uint64_t>(group, 65535u >> hmax);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != j->device) return fail(STEM_EINVAL, "join was created on another device");
+  const int out_log = j->a_log + j->b_log;
+  const uint64_t n_out = 1ull << out_log;
+  if (!(flags & STEM_ACCUMULATE)) {
+    hipError_t e = launch_zero_f64(out, 2 * n_out * n_batch, st);
+    if (e != hipSuccess) return fail(STEM_EHIP, std::string("zero: ") + hipGetErrorString(e));
+  }
+  if (s0 == s1) return STEM_OK;
+  unsigned char* base = (unsigned char*)ws;
+  unsigned char* ws_l = base;
+  unsigned char* ws_r = ws_l + q.chain_l * group;
+  unsigned char* t_l = ws_r + q.chain_r * group;
+  unsigned char* t_r = t_l + q.tl * group;
+  double* part = (double*)(t_r + q.tr * group);
+  const int nchunks = 1 << (j->k_log - j->chunk_log);
+  std::vector<SliceSel> sel_l(pl->L.steps.size()), sel_r(pr->L.steps.size());
+  for (uint32_t b = 0; b < n_batch; ++b) {
+    const uint64_t pa = proj_assign ? proj_assign[b] : 0;
+    Operand stem_l = plain_operand(pl->d_stem, 0);
+    stem_l.vstride = (int64_t)(8 * pl->stem_var_elems);
+    stem_l.sel = make_sel(pl->L.stem_fixed_src, pa, n_sl, n_pr);
+    for (size_t i = 0; i < pl->L.steps.size(); ++i)
+      sel_l[i] = make_sel(pl->L.steps[i].fixed_src, pa, n_sl, n_pr);
+    Operand stem_r = plain_operand(pr->d_stem, 0);
+    stem_r.vstride = (int64_t)(8 * pr->stem_var_elems);
+    stem_r.sel = make_sel(pr->L.stem_fixed_src, pa, n_sl, n_pr);
+    for (size_t i = 0; i < pr->L.steps.size(); ++i)
+      sel_r[i] = make_sel(pr->L.steps[i].fixed_src, pa, n_sl, n_pr);
+    for (uint64_t c0 = s0; c0 < s1; c0 += group) {
+      const int nz = (int)std::min<uint64_t>(group, s1 - c0);
+      Operand fl, fr;
+      int buf = -1;
+      stem_status rs = run_chain(pl, stem_l, sel_l, c0, nz, ws_l, (int64_t)(q.chain_l / 2),
+                                 (int64_t)(q.chain_l / 2 * group), false, st, &fl, &buf);
+      if (rs != STEM_OK) return rs;
+      rs = run_chain(pr, stem_r, sel_r, c0, nz, ws_r, (int64_t)(q.chain_r / 2),
+                     (int64_t)(q.chain_r / 2 * group), false, st, &fr, &buf);
+      if (rs != STEM_OK) return rs;
+      if (j->perm_left) {
+        const Operand o = plain_operand(t_l, (int64_t)q.tl);
+        hipError_t e = launch_permute(fl, o, j->pl, c0, nz, st);
+        if (e != hipSuccess) return fail(STEM_EHIP, std::string("permute: ") + hipGetErrorString(e));
+        fl = o;
+      }
+      if (j->perm_right) {
+        const Operand o = plain_operand(t_r, (int64_t)q.tr);
+        hipError_t e = launch_permute(fr, o, j->pr, c0, nz, st);
+        if (e != hipSuccess) return fail(STEM_EHIP, std::string("permute: ") + hipGetErrorString(e));
+        fr = o;
+      }
+      hipError_t e = launch_join_partial(fl, fr, c0, nz, j->a_log, j->b_log, j->k_log,
+                                         j->chunk_log, part, st);
+      if (e != hipSuccess) return fail(STEM_EHIP, std::string("join: ") + hipGetErrorString(e));
+      e = launch_join_acc(part, nz, nchunks, out_log, out + 2 * n_out * b, j->out_map, st);
+      if (e != hipSuccess) return fail(STEM_EHIP, std::string("join sum: ") + hipGetErrorString(e));
+    }
+  }
   return STEM_OK;
 }
 
@@ -671,6 +816,88 @@ stem_status stem_contract(stem_plan_t p, uint64_t s0, uint64_t s1, const uint64_
                           uint32_t flags, void* stream) {
   return contract_impl(p, s0, s1, proj_assign, n_batch, ws, ws_bytes, out, flags,
                        (hipStream_t)stream);
+}
+
+stem_status stem_join_create(stem_plan_t left, stem_plan_t right, int32_t n_open,
+                             const int32_t* open_labels, stem_join_t* join) {
+  if (!join) return fail(STEM_EINVAL, "null join output");
+  *join = nullptr;
+  if (!left || !right) return fail(STEM_EINVAL, "null plan");
+  if (n_open < 0 || (n_open && !open_labels)) return fail(STEM_EINVAL, "bad open label list");
+  if (left->device != right->device) return fail(STEM_EINVAL, "plans on different devices");
+  const PlanLayout &A = left->L, &B = right->L;
+  if (A.sliced != B.sliced || A.proj != B.proj)
+    return fail(STEM_ELABEL, "the two plans must list the same sliced and projected labels");
+  std::set<int32_t> la(A.open.begin(), A.open.end()), lb(B.open.begin(), B.open.end());
+  std::vector<int32_t> shared, only_a, only_b;
+  for (int32_t x : A.final_labels) (lb.count(x) ? shared : only_a).push_back(x);
+  for (int32_t x : B.final_labels)
+    if (!la.count(x)) only_b.push_back(x);
+  std::vector<int32_t> open(open_labels, open_labels + n_open);
+  std::set<int32_t> want(open.begin(), open.end());
+  std::set<int32_t> sym(only_a.begin(), only_a.end());
+  sym.insert(only_b.begin(), only_b.end());
+  if (want.size() != open.size() || want != sym)
+    return fail(STEM_ELABEL, "the join's open labels must be the labels open in exactly one plan");
+  if (n_open > kJoinMaxOpenLog)
+    return fail(STEM_EUNSUPPORTED, "a join has at most 12 open labels");
+  stem_join_s* j = nullptr;
+  try {
+    j = new stem_join_s();
+  } catch (const std::bad_alloc&) {
+    return fail(STEM_ENOMEM, "host allocation failed");
+  }
+  j->left = left;
+  j->right = right;
+  j->device = left->device;
+  j->open = open;
+  j->left_order = shared;
+  j->left_order.insert(j->left_order.end(), only_a.begin(), only_a.end());
+  j->right_order = shared;
+  j->right_order.insert(j->right_order.end(), only_b.begin(), only_b.end());
+  j->perm_left = !same_order(A.final_labels, j->left_order);
+  j->perm_right = !same_order(B.final_labels, j->right_order);
+  if (j->perm_left) j->pl = make_perm(A.final_labels, j->left_order);
+  if (j->perm_right) j->pr = make_perm(B.final_labels, j->right_order);
+  j->a_log = (int)only_a.size();
+  j->b_log = (int)only_b.size();
+  j->k_log = (int)shared.size();
+  // at most 256 chunks of at least 256 k values (all of k when shorter)
+  j->chunk_log = j->k_log <= 8 ? j->k_log : std::max(8, j->k_log - 8);
+  // output index a 2^b_log + b -> position of each label in the join's order
+  const int r = n_open;
+  j->out_map.rank = r;
+  auto pos_of = [&](int32_t x) {
+    int k = 0;
+    while (open[k] != x) ++k;
+    return r - 1 - k;
+  };
+  for (int t = 0; t < j->b_log; ++t) j->out_map.dst[j->b_log - 1 - t] = pos_of(only_b[t]);
+  for (int t = 0; t < j->a_log; ++t)
+    j->out_map.dst[j->b_log + j->a_log - 1 - t] = pos_of(only_a[t]);
+  *join = j;
+  return STEM_OK;
+}
+
+stem_status stem_join_workspace_bytes(stem_join_t join, uint32_t slices_in_flight,
+                                      uint64_t* bytes) {
+  if (!join || !bytes) return fail(STEM_EINVAL, "null argument");
+  if (slices_in_flight < 1 || slices_in_flight > (uint32_t)kMaxSlicesInFlight)
+    return fail(STEM_ERANGE, "slices_in_flight outside [1, 4096]");
+  *bytes = join_parts(join).total() * slices_in_flight;
+  return STEM_OK;
+}
+
+stem_status stem_join_contract(stem_join_t join, uint64_t s0, uint64_t s1,
+                               const uint64_t* proj_assign, uint32_t n_batch, void* ws,
+                               uint64_t ws_bytes, double* out, uint32_t flags, void* stream) {
+  return join_contract_impl(join, s0, s1, proj_assign, n_batch, ws, ws_bytes, out, flags,
+                            (hipStream_t)stream);
+}
+
+stem_status stem_join_destroy(stem_join_t join) {
+  delete join;
+  return STEM_OK;
 }
 
 stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_t* s0,

@@ -49,6 +49,18 @@ hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const
 hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, const BitMap& m,
                           hipStream_t st);
 hipError_t launch_zero_f64(double* p, uint64_t n, hipStream_t st);
+// Root join of two stem halves, split over K: for every slice z < nz and
+// chunk c of 2^chunk_log k values, part[(z * nchunks + c) * 2^(a+b) + o]
+// = sum over k in the chunk of L_z[k][a] R_z[k][b] (o = a 2^b_log + b),
+// complex, accumulated in FP64; L_z is [2^k_log][2^a_log] and R_z is
+// [2^k_log][2^b_log] complex64, row-major; a_log + b_log <= 12.
+hipError_t launch_join_partial(const Operand& L, const Operand& R, uint64_t s0, int nz, int a_log,
+                               int b_log, int k_log, int chunk_log, double* part,
+                               hipStream_t st);
+// out[m(o)] += sum over z < nz (in order) of (sum over chunks, in order, of
+// part[z][c][o]).
+hipError_t launch_join_acc(const double* part, int nz, int nchunks, int out_log, double* out,
+                           const BitMap& m, hipStream_t st);
 hipError_t launch_fill_counter(float* dst, uint64_t n, uint64_t seed, int scale_log2,
                                hipStream_t st);
 hipError_t launch_xeb_f64(const double* amps, uint64_t n, int n_qubits, double* out,

@@ -211,6 +211,110 @@ hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, c
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Root join of two stem halves (the contraction of the two final tensors
+// over the labels they share).  The output is small (the open labels) and
+// the shared index long, so the work is split over k: every workgroup
+// takes one slice and one chunk of k, stages the chunk's rows of L and R
+// in LDS (both k-major, so every stage is one contiguous run of each), and
+// every thread sums the products of its outputs in FP64.
+// ---------------------------------------------------------------------------
+constexpr int kJoinStageLog = 8;       // k values per LDS stage, at most
+constexpr int kJoinLds = 64 * 1024;     // LDS of one stage, at most
+
+__global__ __launch_bounds__(256) void stem_join_partial_kernel(Operand Lop, Operand Rop,
+                                                                uint64_t s0, int a_log, int b_log,
+                                                                int k_log, int chunk_log,
+                                                                int stage_log,
+                                                                double2* __restrict__ part) {
+  extern __shared__ float2 sj[];
+  const int z = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const float2* __restrict__ L = (const float2*)op_base(Lop, z, s0);
+  const float2* __restrict__ R = (const float2*)op_base(Rop, z, s0);
+  const int na = 1 << a_log, nb = 1 << b_log;
+  const int n_out = na * nb;
+  const int64_t k0 = (int64_t)chunk << chunk_log;
+  const int kn = 1 << chunk_log;
+  const int stage = 1 << stage_log;       // <= kn
+  float2* sL = sj;                       // [stage][na]
+  float2* sR = sj + (size_t)stage * na;  // [stage][nb]
+  double2 acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int kk = 0; kk < kn; kk += stage) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < stage * na; i += blockDim.x) sL[i] = L[(k0 + kk) * na + i];
+    for (int i = threadIdx.x; i < stage * nb; i += blockDim.x) sR[i] = R[(k0 + kk) * nb + i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int o = threadIdx.x + q * 256;
+      if (o < n_out) {
+        const int a = o >> b_log, b = o & (nb - 1);
+        double re = acc[q].x, im = acc[q].y;
+        for (int k = 0; k < stage; ++k) {
+          const float2 l = sL[k * na + a];
+          const float2 r = sR[k * nb + b];
+          re += (double)l.x * r.x - (double)l.y * r.y;
+          im += (double)l.x * r.y + (double)l.y * r.x;
+        }
+        acc[q] = make_double2(re, im);
+      }
+    }
+  }
+  const int nchunks = 1 << (k_log - chunk_log);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int o = threadIdx.x + q * 256;
+    if (o < n_out) part[((int64_t)z * nchunks + chunk) * n_out + o] = acc[q];
+  }
+}
+
+hipError_t launch_join_partial(const Operand& L, const Operand& R, uint64_t s0, int nz, int a_log,
+                               int b_log, int k_log, int chunk_log, double* part,
+                               hipStream_t st) {
+  const int na = 1 << a_log, nb = 1 << b_log;
+  int stage_log = std::min(chunk_log, kJoinStageLog);
+  while (stage_log > 0 && (size_t)(na + nb) * ((size_t)8 << stage_log) > (size_t)kJoinLds)
+    --stage_log;
+  const size_t lds = (size_t)(na + nb) * ((size_t)8 << stage_log);
+  const int nchunks = 1 << (k_log - chunk_log);
+  hipLaunchKernelGGL(stem_join_partial_kernel, dim3((unsigned)nchunks, (unsigned)nz), dim3(256),
+                     lds, st, L, R, s0, a_log, b_log, k_log, chunk_log, stage_log,
+                     (double2*)part);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void stem_join_acc_kernel(const double2* __restrict__ part,
+                                                            int nz, int nchunks, int n_out,
+                                                            double2* __restrict__ out, BitMap m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_out) return;
+  uint64_t o = 0;
+  for (int q = 0; q < m.rank; ++q) o |= ((uint64_t)(i >> q) & 1ull) << m.dst[q];
+  double2 r = out[o];
+  for (int z = 0; z < nz; ++z) {
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+      const double2 v = part[((int64_t)z * nchunks + c) * n_out + i];
+      re += v.x;
+      im += v.y;
+    }
+    r.x += re;
+    r.y += im;
+  }
+  out[o] = r;
+}
+
+hipError_t launch_join_acc(const double* part, int nz, int nchunks, int out_log, double* out,
+                           const BitMap& m, hipStream_t st) {
+  const int n_out = 1 << out_log;
+  hipLaunchKernelGGL(stem_join_acc_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0,
+                     st, (const double2*)part, nz, nchunks, n_out, (double2*)out, m);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void stem_zero_f64_kernel(double* __restrict__ p, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;

@@ -198,11 +198,6 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
       *err = "open label " + std::to_string(x) + " occurs in no tensor";
       return STEM_ELABEL;
     }
-  for (auto& kv : fixed)
-    if (count[kv.first] < 1) {
-      *err = "sliced or projected label " + std::to_string(kv.first) + " occurs in no tensor";
-      return STEM_ELABEL;
-    }
   for (auto& kv : count) {
     if (open_set.count(kv.first) || fixed.count(kv.first)) continue;
     if (kv.second < 2) {

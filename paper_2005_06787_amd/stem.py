@@ -220,6 +220,72 @@ class Plan:
             pass
 
 
+class Join:
+    """Two plans joined at the root (C-ABI stem_join_*, paper §A.2): per
+    slice, the two final stems are contracted over the labels open in both;
+    ``open_labels`` (the labels open in exactly one plan) orders the result."""
+
+    def __init__(self, left: Plan, right: Plan, open_labels):
+        self.left, self.right = left, right
+        self.open = [int(x) for x in open_labels]
+        self.n_open = len(self.open)
+        self.n_sliced = left.n_sliced
+        arr = _i32(self.open)
+        h = ctypes.c_void_p()
+        C.check(C.lib().stem_join_create(left._h, right._h, self.n_open,
+                                         _ptr(arr, ctypes.c_int32), ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+
+    def workspace_bytes(self, slices_in_flight: int = 1) -> int:
+        b = ctypes.c_uint64()
+        C.check(C.lib().stem_join_workspace_bytes(self._h, int(slices_in_flight),
+                                                  ctypes.byref(b)))
+        return int(b.value)
+
+    def contract(self, s0: int = 0, s1: int | None = None, proj=None, out=None,
+                 accumulate: bool = False, stream=None, slices_in_flight: int | None = None):
+        """Sum over slices [s0, s1) of the joined value, per projected
+        assignment: a complex128 CUDA tensor [n_batch, 2^n_open]."""
+        import torch
+
+        if s1 is None:
+            s1 = 1 << self.n_sliced
+        if slices_in_flight is None:
+            per = max(1, self.workspace_bytes(1))
+            slices_in_flight = int(max(1, min(max(1, s1 - s0), 256, (16 << 30) // per)))
+        proj_arr = np.ascontiguousarray(np.asarray(list(proj if proj is not None else [0]),
+                                                   dtype=np.uint64))
+        nb = len(proj_arr)
+        if out is None:
+            out = torch.empty((nb, 1 << self.n_open), dtype=torch.complex128, device="cuda")
+        if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous()
+                and out.numel() == nb << self.n_open):
+            raise ValueError("out must be a contiguous complex128 CUDA tensor [n_batch, 2^n_open]")
+        need = self.workspace_bytes(slices_in_flight)
+        if self._ws is None or self._ws.numel() != need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        C.check(C.lib().stem_join_contract(
+            self._h, int(s0), int(s1), _ptr(proj_arr, ctypes.c_uint64), nb,
+            ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+            ctypes.c_void_p(out.data_ptr()), C.STEM_ACCUMULATE if accumulate else 0,
+            _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            C.lib().stem_join_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Slice ranges of several plans recorded as one HIP graph (C-ABI
     stem_batch_*).  ``launch()`` replays it: every plan's output is

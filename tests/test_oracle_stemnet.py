@@ -139,3 +139,53 @@ def test_hyperedge_slices_equal_bruteforce(seed):
             ref = tn.value_bruteforce(_fixed_network(plan, assign), plan["open_labels"])
             got, _ = stemnet.run_slice(plan, s, p)
             assert np.allclose(got, ref, atol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 7, 8, 9])
+def test_join_slice_equals_bruteforce(seed):
+    """Two stems joined at the root (paper §A.2): cutting a network into a
+    left stem (stem and first branches) and a right stem (the other
+    branches), and contracting their slice values over the shared labels,
+    gives the path sum of the whole network at every slice and projected
+    assignment, whatever the cut."""
+    from workloads.networks import random_stem_network, split_stem_network
+
+    plan = random_stem_network(400 + seed, stem_rank=5, n_steps=5, s_range=(1, 3),
+                               f_range=(0, 2), n_sliced=2, n_proj=1, rank_bounds=(2, 7),
+                               batch_prob=0.4, n_open_final=3, dtype=np.complex128)
+    cuts = 0
+    for h in range(1, len(plan["branches"])):
+        try:
+            left, right = split_stem_network(plan, h)
+        except ValueError:
+            continue
+        cuts += 1
+        for p in range(1 << len(plan["proj_labels"])):
+            for s in range(1 << len(plan["sliced_labels"])):
+                assign = stemnet.slice_assignment(plan, s)
+                assign.update(stemnet.proj_assignment(plan, p))
+                ref = tn.value_bruteforce(_fixed_network(plan, assign), plan["open_labels"])
+                got = stemnet.join_slice(left, right, plan["open_labels"], s, p)
+                assert np.allclose(got, ref, atol=1e-10), (h, s, p)
+        total = stemnet.join_sliced_sum(left, right, plan["open_labels"])
+        assert np.allclose(total, stemnet.sliced_sum(plan), atol=1e-10)
+    assert cuts >= 1
+
+
+def test_join_of_two_vectors_is_their_inner_product():
+    """Special case written out: two rank-3 stems without branches sharing
+    labels 1 and 2, joined over them, are the matrix sum over x1, x2 of
+    l[x0, x1, x2] r[x2, x1, x5], ordered (x5, x0)."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    lv = _rand(rng, 3)
+    rv = _rand(rng, 3)
+    left = {"open_labels": [0, 1, 2], "sliced_labels": [], "proj_labels": [],
+            "stem": {"labels": [0, 1, 2], "data": lv}, "branches": []}
+    right = {"open_labels": [2, 1, 5], "sliced_labels": [], "proj_labels": [],
+             "stem": {"labels": [2, 1, 5], "data": rv}, "branches": []}
+    got = stemnet.join_slice(left, right, [5, 0])
+    ref = np.zeros((2, 2), dtype=np.complex128)
+    for x5 in range(2):
+        for x0 in range(2):
+            ref[x5, x0] = sum(lv[x0, x1, x2] * rv[x2, x1, x5] for x1 in range(2) for x2 in range(2))
+    assert np.allclose(got, ref, atol=1e-13)

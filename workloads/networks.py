@@ -122,3 +122,40 @@ def random_stem_network(seed: int, stem_rank: int = 8, n_steps: int = 6, *,
                  "data": np.ascontiguousarray(stem_data).astype(dtype)},
         "branches": branches,
     }
+
+
+def split_stem_network(net: dict, h: int) -> tuple[dict, dict]:
+    """Cut a stem network into two stems that meet at the root (structure
+    only): the left one is the stem and branches [0, h), the right one has
+    branch h as its initial stem and branches (h, n) after it.  Each half
+    keeps open the labels it shares with the other half and the network's
+    open labels it carries; both list the network's sliced and projected
+    labels.  The labels open in exactly one half are the network's open
+    labels, which is checked: an open label carried by both halves (a
+    hyperedge at the root) raises ValueError.
+    """
+    br = net["branches"]
+    if not 1 <= h < len(br):
+        raise ValueError("split point outside [1, n_branches)")
+    fixed = set(net["sliced_labels"]) | set(net["proj_labels"])
+    opened = set(net["open_labels"])
+    left_t = [net["stem"]] + br[:h]
+    right_t = br[h:]
+
+    def labels_of(ts):
+        seen = []
+        for t in ts:
+            for x in t["labels"]:
+                if x not in seen:
+                    seen.append(int(x))
+        return seen
+
+    ll, rl = labels_of(left_t), labels_of(right_t)
+    if any(x in opened and x in rl for x in ll):
+        raise ValueError("an open label is carried by both halves")
+    l_open = [x for x in ll if x not in fixed and (x in opened or x in rl)]
+    r_open = [x for x in rl if x not in fixed and (x in opened or x in ll)]
+    common = {"sliced_labels": list(net["sliced_labels"]), "proj_labels": list(net["proj_labels"])}
+    left = dict(common, open_labels=l_open, stem=net["stem"], branches=list(br[:h]))
+    right = dict(common, open_labels=r_open, stem=br[h], branches=list(br[h + 1:]))
+    return left, right
