@@ -256,6 +256,75 @@ def locally_optimised_30q(steps: int, tune_cache=None):
     return out
 
 
+def two_sided_30q(steps: int, tune_cache=None):
+    """The headline circuit's scheme (same order and sliced labels) as two
+    stems meeting at the root: the left stem grows from the start of the
+    order, the right stem from its end, and the join contracts them over
+    the cut.  Two cuts: the one with the smallest modelled time (roofline
+    of both sides' products plus the join) and the earliest one modelled
+    within 5 % of it (a long shared index); all 2^10 slices, FP32."""
+    import torch
+
+    from paper_2005_06787_amd import Join, Plan, planner
+    from paper_2005_06787_amd.stem import stem_plan_validate
+    from workloads import configs
+
+    cfg = configs.CIRCUIT_CONFIGS["c2_5x6_m14"]
+    circ, oq, closed = configs.circuit_case(cfg)
+    pb = planner.CircuitProblem(circ, oq, closed)
+    order, sliced, _, _ = planner.find_scheme(pb.tlabels, 64, 0, n_sliced=cfg["n_sliced"],
+                                              forbid=pb.forbid)
+    cand = []
+    for h in range(len(order) // 2, len(order) - 1):
+        try:
+            left, right, _ = planner.two_sided_networks(pb, order, sliced, h, with_data=False)
+            sl, sr = stem_plan_validate(left), stem_plan_validate(right)
+        except Exception:   # a side above the rank limits
+            continue
+        k = len(set(left["open_labels"]) & set(right["open_labels"]))
+        a, b = len(left["open_labels"]) - k, len(right["open_labels"]) - k
+        by = sl["bytes_per_slice"] + sr["bytes_per_slice"] + 8.0 * 2 ** k * (2 ** a + 2 ** b)
+        fl = sl["flops_per_slice"] + sr["flops_per_slice"] + 8.0 * 2 ** (k + a + b)
+        cand.append((max(by / 5e12, fl / 1.2e14), h, fl))
+    t_best = min(c[0] for c in cand)
+    best = min(cand)
+    deep = min((c for c in cand if c[0] <= 1.05 * t_best), key=lambda c: c[1])
+    one = planner.scheme_network(pb, order, sliced)
+    p1 = Plan(one)
+    n = 1 << p1.n_sliced
+    ref = p1.contract(0, n).cpu().numpy()[0]
+    p1.close()
+    out = {"workload": "5x6 grid, 14 cycles, 30 qubits, 2^10 slices, headline scheme as two "
+                       "stems joined at the root, FP32", "n_tensors": len(order)}
+    for name, (_, h, flops) in (("best_cut", best), ("early_cut", deep)):
+        left, right, op = planner.two_sided_networks(pb, order, sliced, h)
+        pl, pr = Plan(left), Plan(right)
+        g = min(pl.default_slices_in_flight(n), pr.default_slices_in_flight(n))
+        pl.tune(slices_in_flight=g, reps=2, cache_path=tune_cache)
+        pr.tune(slices_in_flight=g, reps=2, cache_path=tune_cache)
+        j = Join(pl, pr, op)
+        res = j.contract(0, n, slices_in_flight=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            j.contract(0, n, out=res, slices_in_flight=g)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        k = len(set(left["open_labels"]) & set(right["open_labels"]))
+        err = float(np.linalg.norm(res.cpu().numpy()[0] - ref) / np.linalg.norm(ref))
+        out[name] = {"cut": h, "shared_labels": k,
+                     "left_peak_rank": pl.summary()["peak_rank"],
+                     "right_peak_rank": pr.summary()["peak_rank"],
+                     "ms_per_step": round(dt * 1e3, 3), "slices_per_s": round(n / dt, 1),
+                     "tflops": round(flops * n / dt / 1e12, 2), "rel_l2_vs_one_sided": err}
+        log(f"two-sided 30-qubit plan, cut {h} of {len(order)} ({k} shared labels): "
+            f"{n / dt:.0f} slices/s, rel L2 vs one-sided {err:.2e}")
+        j.close()
+        pl.close()
+        pr.close()
+    return out
+
+
 def sampling_30q(n_prefixes: int, tune_cache=None):
     """Frugal rejection sampling on the 30-qubit, 14-cycle circuit: random
     prefixes of the 24 closed qubits as projected batch entries (64
@@ -498,6 +567,7 @@ def main():
         line["slice_53q_m20"] = slice_53q(3, args.tune_cache)
         line["sampling_30q"] = sampling_30q(8, args.tune_cache)
         line["locally_optimised_30q"] = locally_optimised_30q(3, args.tune_cache)
+        line["two_sided_30q"] = two_sided_30q(3, args.tune_cache)
     print(json.dumps(line), flush=True)
 
 

@@ -31,6 +31,7 @@ slicing scheme (E_s, T) whose tree T is a stem (§A.1, §A.2):
 from __future__ import annotations
 
 import math
+from types import SimpleNamespace
 
 import numpy as np
 
@@ -501,6 +502,51 @@ def scheme_network(pb: CircuitProblem, order, sliced, *, init_rank: int = 12,
         "branches": branches,
         "stats": st,
     }
+
+
+class _SideProblem:
+    """The tensors of one side of a two-sided scheme, as a problem of its
+    own whose open labels are the side's open labels and its cut labels."""
+
+    def __init__(self, pb: CircuitProblem, idx, open_labels):
+        self.tensors = [pb.tensors[i] for i in idx]
+        self.tlabels = [pb.tlabels[i] for i in idx]
+        self.proj = pb.proj
+        self.forbid = set(open_labels)
+        self.net = SimpleNamespace(open_labels=list(open_labels),
+                                   proj_labels=list(pb.net.proj_labels))
+
+
+def two_sided_networks(pb: CircuitProblem, order, sliced, h: int, **kw):
+    """Two stems meeting at the root (paper §A.2, a root in the middle of
+    the stem): the left stem grows from order[0] through order[h-1], the
+    right stem from the last tensor of the order back to order[h].  Each
+    side keeps open the network's open labels it carries and the unsliced
+    labels between the sides (the cut); the join contracts the two final
+    stems over the cut.  Every cut of the order is the same edge set seen
+    from either side, so each side's stem widths are the one-sided stem's
+    widths on its part of the order.
+
+    Returns (left network, right network, join open labels); ``kw`` goes to
+    ``scheme_network`` for both sides.
+    """
+    n = len(order)
+    if not 1 <= h < n:
+        raise ValueError("cut outside [1, len(order))")
+    left_idx = [int(i) for i in order[:h]]
+    right_idx = [int(i) for i in reversed(order[h:])]
+    fixed = set(sliced) | pb.proj
+    lab_l = _group_labels(pb.tlabels, left_idx) - fixed
+    lab_r = _group_labels(pb.tlabels, right_idx) - fixed
+    cut = sorted(lab_l & lab_r)
+    opened = [int(x) for x in pb.net.open_labels]
+    l_open = [x for x in opened if x in lab_l] + cut
+    r_open = [x for x in opened if x in lab_r] + cut
+    left = scheme_network(_SideProblem(pb, left_idx, l_open), list(range(len(left_idx))),
+                          sliced, **kw)
+    right = scheme_network(_SideProblem(pb, right_idx, r_open), list(range(len(right_idx))),
+                           sliced, **kw)
+    return left, right, opened
 
 
 def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=(), *,

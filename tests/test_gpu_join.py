@@ -157,3 +157,36 @@ def test_join_label_errors():
                                     ctypes.c_void_p(out.data_ptr()), C.STEM_TIME_STEPS, None)
     assert st == C.STEM_EINVAL
     j.close()
+
+
+def test_two_sided_circuit_plan_matches_oracle():
+    """A circuit's scheme cut into two stems meeting at the root (4x5 grid,
+    8 cycles, 6 open qubits, 2^4 slices): the GPU join equals the oracle's
+    join of the same two networks, and the one-sided plan's amplitudes."""
+    from paper_2005_06787_amd import planner
+    from workloads import circuits as wc
+    from workloads import tensors as wt
+
+    c = wc.make_circuit(4, 5, 8, seed=1)
+    open_q = wc.block_qubits(4, 5, range(0, 2), range(2, 5))
+    pre = wt.split_open_prefix(20, open_q, 1001)
+    closed = dict(zip(pre["closed"], pre["closed_bits"]))
+    pb = planner.CircuitProblem(c, open_q, closed)
+    order, sliced, _, _ = planner.find_scheme(pb.tlabels, 8, 0, n_sliced=4, forbid=pb.forbid)
+    one = planner.scheme_network(pb, order, sliced)
+    p1 = Plan(one)
+    ref_one = p1.contract().cpu().numpy()[0]
+    p1.close()
+    m = len(order)
+    for h in (m // 3, m // 2, m - 3):
+        left, right, op = planner.two_sided_networks(pb, order, sliced, h)
+        print(f"circuit cut {h} of {m}", flush=True)
+        pl, pr = Plan(left), Plan(right)
+        j = Join(pl, pr, op)
+        got = j.contract().cpu().numpy()[0]
+        ref = stemnet.join_sliced_sum(_c128(left), _c128(right), op).reshape(-1)
+        assert stats.rel_l2(got, ref) <= 1e-5, h
+        assert stats.rel_l2(got, ref_one) <= 1e-5, h
+        j.close()
+        pl.close()
+        pr.close()

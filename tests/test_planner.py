@@ -239,3 +239,33 @@ def test_refined_scheme_meets_the_target_and_is_no_worse():
     o2, s2, p2, tc2 = planner.find_scheme(pb.tlabels, 4, 0, max_width=9, forbid=pb.forbid,
                                           local_window=4)
     assert (p2, tc2) <= (peak, tc)
+
+
+@pytest.mark.parametrize("rows,cols,cycles,seed,n_sliced", [(3, 3, 5, 2, 2), (2, 4, 8, 4, 1)])
+def test_two_sided_networks_equal_statevector(rows, cols, cycles, seed, n_sliced):
+    """Two stems meeting at the root, cut anywhere along the scheme's
+    order, joined over the cut (the oracle's join), give the state-vector
+    amplitudes for every projected assignment."""
+    c = wc.make_circuit(rows, cols, cycles, seed)
+    n = c["n_qubits"]
+    psi = statevector.run(c)
+    open_q = [0, n - 1]
+    proj_q = [1, n - 2]
+    closed = {q: (q * 7 + seed) % 2 for q in range(n) if q not in open_q + proj_q}
+    pb = planner.CircuitProblem(c, open_q, closed, proj_q)
+    order, sliced, _, _ = planner.find_scheme(pb.tlabels, 4, seed, n_sliced=n_sliced,
+                                              forbid=pb.forbid)
+    m = len(order)
+    for h in sorted({2, m // 3, m // 2, m - 2}):
+        left, right, op = planner.two_sided_networks(pb, order, sliced, h, init_rank=4,
+                                                     max_branch_rank=6)
+        assert left["sliced_labels"] == right["sliced_labels"]
+        assert set(left["open_labels"]) ^ set(right["open_labels"]) == set(op)
+        ol, orr = _c128(left), _c128(right)
+        for p in range(4):
+            bits = {proj_q[0]: (p >> 1) & 1, proj_q[1]: p & 1}
+            cb = {**closed, **bits}
+            closed_q = sorted(cb)
+            ref = statevector.batch_amplitudes(psi, n, open_q, closed_q, [cb[q] for q in closed_q])
+            got = stemnet.join_sliced_sum(ol, orr, op, proj=p).reshape(-1)
+            assert stats.rel_l2(got, ref) < 1e-6, (h, p)
