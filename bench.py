@@ -77,7 +77,8 @@ def make_net():
     oq = configs.open_qubits(cfg)
     pre = tensors.split_open_prefix(circ["n_qubits"], oq, cfg["prefix_seed"])
     closed = dict(zip(pre["closed"], pre["closed_bits"]))
-    net = planner.plan_circuit(circ, oq, closed, n_sliced=cfg["n_sliced"], trials=64, seed=0)
+    net = planner.plan_circuit(circ, oq, closed, n_sliced=cfg["n_sliced"], trials=64, seed=0,
+                               max_branch_rank=cfg["max_branch_rank"])
     return net, cfg
 
 
@@ -231,7 +232,7 @@ def locally_optimised_30q(steps: int, tune_cache=None):
     cfg = configs.CIRCUIT_CONFIGS["c2_5x6_m14"]
     circ, oq, closed = configs.circuit_case(cfg)
     net = planner.plan_circuit(circ, oq, closed, n_sliced=cfg["n_sliced"], trials=64, seed=0,
-                               local_window=5)
+                               local_window=5, max_branch_rank=cfg["max_branch_rank"])
     out = {"workload": "5x6 grid, 14 cycles, 30 qubits, 2^10 slices, plan with local "
                        "optimisation (window 5)"}
     for precision in ("fp32", "split_fp16"):
@@ -274,10 +275,12 @@ def two_sided_30q(steps: int, tune_cache=None):
     pb = planner.CircuitProblem(circ, oq, closed)
     order, sliced, _, _ = planner.find_scheme(pb.tlabels, 64, 0, n_sliced=cfg["n_sliced"],
                                               forbid=pb.forbid)
+    mbr = cfg["max_branch_rank"]
     cand = []
     for h in range(len(order) // 2, len(order) - 1):
         try:
-            left, right, _ = planner.two_sided_networks(pb, order, sliced, h, with_data=False)
+            left, right, _ = planner.two_sided_networks(pb, order, sliced, h, with_data=False,
+                                                        max_branch_rank=mbr)
             sl, sr = stem_plan_validate(left), stem_plan_validate(right)
         except Exception:   # a side above the rank limits
             continue
@@ -289,7 +292,7 @@ def two_sided_30q(steps: int, tune_cache=None):
     t_best = min(c[0] for c in cand)
     best = min(cand)
     deep = min((c for c in cand if c[0] <= 1.05 * t_best), key=lambda c: c[1])
-    one = planner.scheme_network(pb, order, sliced)
+    one = planner.scheme_network(pb, order, sliced, max_branch_rank=mbr)
     p1 = Plan(one)
     n = 1 << p1.n_sliced
     ref = p1.contract(0, n).cpu().numpy()[0]
@@ -297,7 +300,7 @@ def two_sided_30q(steps: int, tune_cache=None):
     out = {"workload": "5x6 grid, 14 cycles, 30 qubits, 2^10 slices, headline scheme as two "
                        "stems joined at the root, FP32", "n_tensors": len(order)}
     for name, (_, h, flops) in (("best_cut", best), ("early_cut", deep)):
-        left, right, op = planner.two_sided_networks(pb, order, sliced, h)
+        left, right, op = planner.two_sided_networks(pb, order, sliced, h, max_branch_rank=mbr)
         pl, pr = Plan(left), Plan(right)
         g = min(pl.default_slices_in_flight(n), pr.default_slices_in_flight(n))
         pl.tune(slices_in_flight=g, reps=2, cache_path=tune_cache)
@@ -339,7 +342,7 @@ def sampling_30q(n_prefixes: int, tune_cache=None):
     n = circ["n_qubits"]
     closed_q = [q for q in range(n) if q not in oq]
     net = planner.plan_circuit(circ, oq, None, closed_q, n_sliced=cfg["n_sliced"], trials=64,
-                               seed=0)
+                               seed=0, max_branch_rank=cfg["max_branch_rank"])
     plan = Plan(net)
     plan.tune(slices_in_flight=plan.default_slices_in_flight(1 << plan.n_sliced), reps=2,
               cache_path=tune_cache)

@@ -115,7 +115,8 @@ def c2_plan():
     oq = configs.open_qubits(C2)
     pre = tensors.split_open_prefix(circ["n_qubits"], oq, C2["prefix_seed"])
     closed = dict(zip(pre["closed"], pre["closed_bits"]))
-    return planner.plan_circuit(circ, oq, closed, n_sliced=C2["n_sliced"], trials=64, seed=0)
+    return planner.plan_circuit(circ, oq, closed, n_sliced=C2["n_sliced"], trials=64, seed=0,
+                                max_branch_rank=C2["max_branch_rank"])
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_fp16"])
