@@ -401,7 +401,7 @@ def roofline(plan):
     roof_us = sum(max(nz * s["bytes"] / (HBM_PEAK_GBS * 1e9), nz * s["flops"] / FP32_PEAK_FLOPS)
                   for s in steps) * 1e6
     return {
-        "kernel": "stem_cgemm_f32_kernel",
+        "kernel": "FP32 product launches (stem_cgemm_f32_kernel, stem_cgemm_f32g_kernel)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,

@@ -127,6 +127,9 @@ typedef struct stem_step_info {
   int32_t n_batch;        /* labels the stem and the branch share and keep (a later branch
                              or the result carries them): the product is batched over their
                              2^n_batch values, each with its own branch sub-matrix */
+  int32_t sched_algo;     /* FP32 product arithmetic: 0 real embedding (4 real products per
+                             complex one), 1 the 3M method (3 real products; sched_ntw then
+                             counts 16-complex-column tiles) */
 } stem_step_info;
 
 /* Summary of a plan, computed on the host without a GPU. */
@@ -240,6 +243,22 @@ stem_status stem_batch_create(int32_t n, const stem_plan_t* plans, const uint64_
                               stem_batch_t* batch);
 stem_status stem_batch_launch(stem_batch_t batch, void* stream);
 stem_status stem_batch_destroy(stem_batch_t batch);
+
+/*
+ * Set the launch schedule of step `step` (what stem_tune would pick; paper
+ * §A.3 on the GPU efficiency of small products): tm row blocks per wave (1,
+ * 2, 4), ntw column tiles per workgroup (1, 2, 4, 8; with algo 1: 1, 2, 4
+ * tiles of 16 complex columns), blocks target workgroups (256 .. 65536),
+ * lds (-1, 0, 1 as sched_lds), algo (0 or 1, as sched_algo).  Values the
+ * step's shape cannot use are clamped the way the kernels clamp them
+ * (read back with stem_step_info_get).  STEM_ERANGE for values outside
+ * those sets; STEM_EUNSUPPORTED for algo 1 on a split-precision plan or a
+ * step whose product is not whole 16-column tiles, 8-value k chunks and
+ * 64-row blocks in block order.  Results are the same for every schedule
+ * up to the rounding of the arithmetic chosen.
+ */
+stem_status stem_step_sched_set(stem_plan_t plan, int32_t step, int32_t tm, int32_t ntw,
+                                int32_t blocks, int32_t lds, int32_t algo);
 
 /*
  * Two-sided stems (paper §A.2: a contraction tree whose root joins two

@@ -61,7 +61,7 @@ class stem_step_info(ctypes.Structure):
         ("sched_tm", ctypes.c_int32), ("sched_ntw", ctypes.c_int32),
         ("sched_blocks", ctypes.c_int32), ("sched_lds", ctypes.c_int32),
         ("tuned_us", ctypes.c_float), ("tuned_slices", ctypes.c_int32),
-        ("n_batch", ctypes.c_int32),
+        ("n_batch", ctypes.c_int32), ("sched_algo", ctypes.c_int32),
     ]
 
 
@@ -141,6 +141,9 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_void_p)]),
     "stem_batch_launch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "stem_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "stem_step_sched_set": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32]),
     "stem_join_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_void_p)]),

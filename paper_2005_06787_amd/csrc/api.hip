@@ -226,6 +226,9 @@ static stem_status plan_create_impl(const stem_plan_desc* d, hipStream_t st, ste
       float inv_b = 1.f;
       if (p->precision == STEM_FP32) {
         build_bfrag_f32(re.data() + v * sub, S.K, S.N, (float*)dst);
+        if (bfrag_gauss_floats(S.K, S.N))
+          build_bfrag_gauss(re.data() + v * sub, S.K, S.N,
+                            (float*)dst + bfrag_f32_floats(S.K, S.N));
       } else {
         const int eb = build_bfrag_split(re.data() + v * sub, S.K, S.N,
                                          p->precision == STEM_SPLIT_BF16, (uint16_t*)dst);
@@ -318,6 +321,7 @@ static void fill_info(const StepLayout& S, stem_step_info* info) {
   info->sched_ntw = S.sched.ntw;
   info->sched_blocks = S.sched.blocks;
   info->sched_lds = S.sched.lds;
+  info->sched_algo = S.sched.algo;
   info->tuned_us = -1.f;
 }
 
@@ -400,8 +404,12 @@ void load_cache(const char* path, std::map<TuneKey, TuneBest>* best) {
     TuneKey k;
     GemmSched s;
     float us;
-    if (tag != "stem-tune-v1" || !(f >> k.prec >> k.amode >> k.cmode >> k.lm >> k.lk >> k.ln >>
-                                   k.nz >> s.tm >> s.ntw >> s.blocks >> s.lds >> us)) {
+    const bool v2 = tag == "stem-tune-v2";
+    if ((tag != "stem-tune-v1" && !v2) ||
+        !(f >> k.prec >> k.amode >> k.cmode >> k.lm >> k.lk >> k.ln >> k.nz >> s.tm >> s.ntw >>
+          s.blocks >> s.lds) ||
+        (v2 && !(f >> s.algo)) || !(f >> us)) {
+      if (!f.eof()) f.clear();
       std::string rest;
       std::getline(f, rest);
       continue;
@@ -426,6 +434,32 @@ std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
   const int kq = precision == STEM_FP32 ? 16 : 32;
   const int kc = std::max<int>(kq, (int)(2 * S.K)) / kq;
   std::vector<GemmSched> out;
+  // the 3M FP32 product where its whole-tile shape holds
+  if (precision == STEM_FP32 && S.gemm.cmode == 1 && S.K % 8 == 0 && S.N % 16 == 0 &&
+      S.M % 64 == 0) {
+    const int ntc_all = (int)(S.N / 16);
+    const int top = std::min(4, ntc_all);
+    for (int tm : {1, 2, 4}) {
+      if (S.M % (64 * tm) != 0) continue;
+      for (int w : {top, top / 2}) {
+        if (w < 1 || tm * w > 4) continue;
+        for (int blocks : {1024, 4096, 16384}) {
+          const size_t lds = (size_t)kc * w * 1536;
+          for (int l : {-1, 0, 1}) {
+            if (l == 0 && lds > (size_t)kLdsBudget) continue;
+            if (l == 1 && (lds <= (size_t)kLdsBudget || lds > lds_limit())) continue;
+            GemmSched s;
+            s.tm = tm;
+            s.ntw = w;
+            s.blocks = blocks;
+            s.lds = l;
+            s.algo = 1;
+            out.push_back(s);
+          }
+        }
+      }
+    }
+  }
   for (int tm : {1, 2, 4})
     for (int w : ntws)
       for (int blocks : {1024, 4096, 16384}) {
@@ -447,6 +481,29 @@ std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
 }  // namespace
 
 extern "C" {
+
+stem_status stem_step_sched_set(stem_plan_t p, int32_t step, int32_t tm, int32_t ntw,
+                                int32_t blocks, int32_t lds, int32_t algo) {
+  if (!p) return fail(STEM_EINVAL, "null plan");
+  if (step < 0 || step >= (int32_t)p->L.steps.size()) return fail(STEM_ERANGE, "step index");
+  if ((tm != 1 && tm != 2 && tm != 4) || (ntw != 1 && ntw != 2 && ntw != 4 && ntw != 8) ||
+      blocks < 256 || blocks > 65536 || lds < -1 || lds > 1 || algo < 0 || algo > 1 ||
+      (algo == 1 && ntw > 4))
+    return fail(STEM_ERANGE, "schedule value outside its set");
+  StepLayout& S = p->L.steps[step];
+  if (algo == 1 && (p->precision != STEM_FP32 || S.gemm.cmode != 1 || S.K % 8 != 0 ||
+                    S.N % 16 != 0 || S.M % 64 != 0))
+    return fail(STEM_EUNSUPPORTED, "the 3M product needs FP32 and whole tiles");
+  GemmSched s;
+  s.tm = tm;
+  s.ntw = ntw;
+  s.blocks = blocks;
+  s.lds = lds;
+  s.algo = algo;
+  const GemmGeom g = make_geom(S.gemm, S.M, S.K, S.N, p->precision == STEM_FP32 ? 16 : 32);
+  S.sched = resolve_sched(g, s);
+  return STEM_OK;
+}
 
 stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, int32_t reps,
                       const char* cache_path, void* stream) {
@@ -513,9 +570,9 @@ stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, i
       }
       const float us = ms * 1000.f / (float)nrep;
       if (log.is_open())
-        log << "stem-tune-v1 " << key.prec << ' ' << key.amode << ' ' << key.cmode << ' '
+        log << "stem-tune-v2 " << key.prec << ' ' << key.amode << ' ' << key.cmode << ' '
             << key.lm << ' ' << key.lk << ' ' << key.ln << ' ' << key.nz << ' ' << c.tm << ' '
-            << c.ntw << ' ' << c.blocks << ' ' << c.lds << ' ' << us << '\n';
+            << c.ntw << ' ' << c.blocks << ' ' << c.lds << ' ' << c.algo << ' ' << us << '\n';
       if (us < win.us) {
         win.us = us;
         win.sched = c;

@@ -217,8 +217,27 @@ static inline GemmGeom make_geom(const GemmLayout& lay, int64_t M, int64_t K, in
   return g;
 }
 
+// True when the 3M FP32 product applies: whole 16-complex-column tiles,
+// whole 8-complex k chunks, output in block order, whole row blocks.
+static inline bool gauss_ok(const GemmGeom& g, int cmode) {
+  return cmode == 1 && g.K % 8 == 0 && g.N % 16 == 0 && g.M % 64 == 0;
+}
+
 // Schedule with the defaults filled in (see GemmSched).
 static inline GemmSched resolve_sched(const GemmGeom& g, GemmSched s) {
+  if (s.algo == 1) {
+    const int ntc_all = g.NT >> 1;
+    if (s.ntw <= 0) s.ntw = std::min(4, ntc_all);
+    s.ntw = std::min(s.ntw, std::min(4, ntc_all));
+    while (s.ntw & (s.ntw - 1)) s.ntw &= s.ntw - 1;
+    if (s.tm <= 0) s.tm = 1;
+    s.tm = s.tm >= 4 ? 4 : s.tm >= 2 ? 2 : 1;
+    while (s.tm > 1 && g.M % (64 * s.tm) != 0) s.tm >>= 1;
+    while (s.tm * s.ntw > 4) s.ntw >>= 1;  // register budget: 3 accumulators per pair
+    if (s.blocks <= 0) s.blocks = kTargetBlocks;
+    return s;
+  }
+  s.algo = 0;
   int nt2 = 1;
   while (nt2 < g.NT) nt2 <<= 1;
   if (s.ntw <= 0) s.ntw = std::min(8, nt2);
@@ -280,6 +299,7 @@ struct LaunchCtx {
 
 // Product launchers, one translation unit per arithmetic.
 void launch_gemm_f32(const LaunchCtx& c, const GemmLayout& lay);
+void launch_gemm_f32g(const LaunchCtx& c, const GemmLayout& lay);
 void launch_gemm_split(const LaunchCtx& c, const GemmLayout& lay, int bf16);
 
 }  // namespace stem

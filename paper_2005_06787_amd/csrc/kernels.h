@@ -23,6 +23,11 @@ namespace stem {
 // expanded B'[16 kc + 4 (lane/16) + j][16 nt + lane%16] (zero padded).
 size_t bfrag_f32_floats(int64_t K, int64_t N);
 void build_bfrag_f32(const float* b, int64_t K, int64_t N, float* out);
+// 3M fragments (C, D, C + D per k chunk and 16-column tile) of a [K x N]
+// complex branch, stored after the real-embedding ones; zero floats unless
+// K % 8 == 0 and N % 16 == 0.
+size_t bfrag_gauss_floats(int64_t K, int64_t N);
+void build_bfrag_gauss(const float* b, int64_t K, int64_t N, float* out);
 
 // Split paths: fragment order for the 16x16x32 f16/bf16 MFMA.  Kq =
 // max(32, 2K), Np = max(16, 2N); 8 consecutive halves per lane:

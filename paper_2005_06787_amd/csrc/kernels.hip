@@ -80,9 +80,30 @@ size_t bfrag_split_halves(int64_t K, int64_t N) {
   return (size_t)(Kq * Np);
 }
 
+size_t bfrag_gauss_floats(int64_t K, int64_t N) {
+  return (K % 8 == 0 && N % 16 == 0) ? (size_t)(3 * K * N) : 0;
+}
+
 size_t branch_block_bytes(int precision, int64_t K, int64_t N) {
-  size_t body = precision == STEM_FP32 ? bfrag_f32_floats(K, N) * 4 : bfrag_split_halves(K, N) * 4;
+  size_t body = precision == STEM_FP32 ? (bfrag_f32_floats(K, N) + bfrag_gauss_floats(K, N)) * 4
+                                       : bfrag_split_halves(K, N) * 4;
   return (kBranchHeader + body + 255) & ~size_t(255);
+}
+
+void build_bfrag_gauss(const float* b, int64_t K, int64_t N, float* out) {
+  const int64_t KC = K / 8, NTC = N / 16;
+  for (int64_t kc = 0; kc < KC; ++kc)
+    for (int64_t ct = 0; ct < NTC; ++ct)
+      for (int j = 0; j < 2; ++j)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t k = 8 * kc + 2 * (lane >> 4) + j;
+          const int64_t n = 16 * ct + (lane & 15);
+          const float br = b[2 * (k * N + n)], bi = b[2 * (k * N + n) + 1];
+          float* o = out + ((kc * NTC + ct) * 6 + 3 * j) * 64 + lane;
+          o[0] = br;
+          o[64] = bi;
+          o[128] = br + bi;
+        }
 }
 
 // Expanded real entry B'[kr][nr] of a complex [K x N] matrix b (interleaved).
@@ -171,8 +192,12 @@ hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const
   c.nz = nz;
   c.st = st;
   c.g = make_geom(lay, M, K, N, precision == STEM_FP32 ? 16 : 32);
-  c.sch = resolve_sched(c.g, sched);
-  if (precision == STEM_FP32)
+  GemmSched want = sched;
+  if (want.algo == 1 && (precision != STEM_FP32 || !gauss_ok(c.g, lay.cmode))) want.algo = 0;
+  c.sch = resolve_sched(c.g, want);
+  if (precision == STEM_FP32 && c.sch.algo == 1)
+    launch_gemm_f32g(c, lay);
+  else if (precision == STEM_FP32)
     launch_gemm_f32(c, lay);
   else
     launch_gemm_split(c, lay, precision == STEM_SPLIT_BF16);

@@ -65,9 +65,10 @@ struct GemmLayout {
 // about `blocks` workgroups per launch, branch fragments in LDS or not.
 struct GemmSched {
   int32_t tm = 0;       // 1, 2 or 4
-  int32_t ntw = 0;      // 1, 2, 4 or 8
+  int32_t ntw = 0;      // 1, 2, 4 or 8 (algo 1: 16-complex-column tiles, 1, 2 or 4)
   int32_t blocks = 0;   // 256 .. 65536
   int32_t lds = -1;     // branch in LDS: 1 up to the device's 160 KB, 0 never, -1 up to 64 KB
+  int32_t algo = 0;     // FP32 only: 0 real embedding, 1 three real products (3M)
 };
 
 struct GemmGeom {

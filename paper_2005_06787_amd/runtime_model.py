@@ -77,10 +77,11 @@ def read_tune_log(path: str):
     with open(path) as f:
         for line in f:
             p = line.split()
-            if len(p) != 13 or p[0] != "stem-tune-v1":
+            if not ((len(p) == 13 and p[0] == "stem-tune-v1")
+                    or (len(p) == 14 and p[0] == "stem-tune-v2")):
                 continue
             prec, am, cm, lm, lk, ln, nz = (int(x) for x in p[1:8])
-            us = float(p[12])
+            us = float(p[-1])
             key = (prec, am, cm, lm, lk, ln, nz)
             if key not in best or us < best[key]:
                 best[key] = us

@@ -154,6 +154,14 @@ class Plan:
     def steps(self) -> list[dict]:
         return [self.step_info(i) for i in range(self.summary()["n_steps"])]
 
+    def set_schedule(self, step: int, tm: int = 1, ntw: int = 1, blocks: int = 4096,
+                     lds: int = -1, algo: int = 0) -> dict:
+        """Set one step's launch schedule (C-ABI stem_step_sched_set); returns
+        the step info with the schedule as the kernels will run it."""
+        C.check(C.lib().stem_step_sched_set(self._h, int(step), int(tm), int(ntw), int(blocks),
+                                            int(lds), int(algo)))
+        return self.step_info(step)
+
     # -- work -------------------------------------------------------------
     def workspace(self, slices_in_flight: int = 1):
         """Device workspace (cached on the plan) for that many slices per launch."""

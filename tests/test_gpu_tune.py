@@ -1,9 +1,11 @@
 """The launch-schedule autotuner (C-ABI stem_tune).
 
-A schedule changes only how rows and column tiles are spread over waves and
-workgroups, never the order in which a product sums, so results after
-tuning must be bit-identical to the defaults; the cache file must hold one
-well-formed line per measurement and be reused without measuring again.
+A schedule's row blocks, column tiles, workgroups and LDS use change only
+how the work is spread, never the order in which a product sums, so results
+after tuning must be bit-identical to the same arithmetic under any other
+such schedule (and to the defaults when no step chose the FP32 3M
+product); the cache file must hold one well-formed line per measurement
+and be reused without measuring again.
 """
 import numpy as np
 import pytest
@@ -40,13 +42,21 @@ def test_tune_keeps_results_and_caches(tmp_path, precision):
     assert len(lines) >= len(steps)
     for line in lines:
         f = line.split()
-        assert f[0] == "stem-tune-v1" and len(f) == 13
+        assert f[0] == "stem-tune-v2" and len(f) == 14
+        assert f[12] in ("0", "1") and (precision == "fp32" or f[12] == "0")
         assert float(f[-1]) > 0
     for s in steps:
         assert s["sched_tm"] in (1, 2, 4) and s["sched_ntw"] in (1, 2, 4, 8)
         assert s["tuned_us"] > 0 and s["tuned_slices"] == n
     after = plan.contract(0, n, proj=[0, 1], slices_in_flight=n)
-    assert torch.equal(before, after)
+    if all(s["sched_algo"] == 0 for s in steps):
+        assert torch.equal(before, after)
+    # the same arithmetic per step under another spread of the work
+    plan3 = Plan(net, precision=precision)
+    for i, s in enumerate(steps):
+        plan3.set_schedule(i, 1, 1, 1024, 0, s["sched_algo"])
+    assert torch.equal(plan3.contract(0, n, proj=[0, 1], slices_in_flight=n), after)
+    plan3.close()
     onet = _c128(net)
     for p in (0, 1):
         ref = stemnet.sliced_sum(onet, proj=p).reshape(-1)
@@ -56,7 +66,8 @@ def test_tune_keeps_results_and_caches(tmp_path, precision):
     steps2 = plan2.tune(slices_in_flight=n, reps=2, cache_path=str(cache))
     assert len([x for x in cache.read_text().split("\n") if x]) == len(lines)
     for a, b in zip(steps, steps2):
-        assert (a["sched_tm"], a["sched_ntw"], a["sched_blocks"], a["sched_lds"]) == \
-            (b["sched_tm"], b["sched_ntw"], b["sched_blocks"], b["sched_lds"])
+        assert (a["sched_tm"], a["sched_ntw"], a["sched_blocks"], a["sched_lds"],
+                a["sched_algo"]) == \
+            (b["sched_tm"], b["sched_ntw"], b["sched_blocks"], b["sched_lds"], b["sched_algo"])
     plan.close()
     plan2.close()

@@ -66,10 +66,12 @@ def test_read_tune_log(tmp_path):
     p.write_text("stem-tune-v1 0 1 1 20 5 5 64 2 4 4096 -1 120.5\n"
                  "stem-tune-v1 0 1 1 20 5 5 64 1 4 4096 -1 100.0\n"
                  "garbage line\n"
-                 "stem-tune-v1 1 0 1 18 3 4 8 4 1 1024 0 7.25\n")
+                 "stem-tune-v1 1 0 1 18 3 4 8 4 1 1024 0 7.25\n"
+                 "stem-tune-v2 0 1 1 20 5 5 64 1 2 4096 -1 1 90.0\n"
+                 "stem-tune-v2 0 1 1 16 3 4 64 1 2 4096 -1 0 3.5\n")
     x, us = rm.read_tune_log(str(p))
-    assert x.shape == (2, rm.N_FEATURES)
-    assert sorted(us.tolist()) == [7.25, 100.0]
+    assert x.shape == (3, rm.N_FEATURES)
+    assert sorted(us.tolist()) == [3.5, 7.25, 90.0]
 
 
 def test_he_init_shapes():
