@@ -121,7 +121,9 @@ typedef struct stem_step_info {
   int32_t sched_tm;       /* launch schedule in use (0 = default): row blocks per wave */
   int32_t sched_ntw;      /* column tiles per workgroup */
   int32_t sched_blocks;   /* target workgroups per launch */
-  int32_t sched_lds;      /* branch in LDS: 1 up to 160 KB, 0 never, -1 up to 64 KB */
+  int32_t sched_lds;      /* branch in LDS: 1 up to 160 KB, 0 never, -1 up to 64 KB; with
+                             sched_algo 1, -1 and 0 also load the next k chunk's fragments
+                             into registers ahead, 1 reads them from LDS where used */
   float tuned_us;         /* stem_tune's time of that schedule per launch, or -1 */
   int32_t tuned_slices;   /* slices per launch stem_tune measured with */
   int32_t n_batch;        /* labels the stem and the branch share and keep (a later branch

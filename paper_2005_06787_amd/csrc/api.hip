@@ -444,10 +444,12 @@ std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
       for (int w : {top, top / 2}) {
         if (w < 1 || tm * w > 4) continue;
         for (int blocks : {1024, 4096, 16384}) {
+          // -1: LDS (up to 64 KB) with prefetch, else global with prefetch;
+          // 0: global with prefetch; 1: LDS up to the device limit, no prefetch
           const size_t lds = (size_t)kc * w * 1536;
           for (int l : {-1, 0, 1}) {
             if (l == 0 && lds > (size_t)kLdsBudget) continue;
-            if (l == 1 && (lds <= (size_t)kLdsBudget || lds > lds_limit())) continue;
+            if (l == 1 && lds > lds_limit()) continue;
             GemmSched s;
             s.tm = tm;
             s.ntw = w;

@@ -235,8 +235,11 @@ static void launch_f32_m(const LaunchCtx& c) {
 // fragments).  Lane (r16, grp) accumulates complex columns 4 grp + r of its
 // tile for row r16 and writes them as 8 consecutive reals.  Whole shapes
 // only: M a multiple of 64 TM, K of 8, N of 16, output in block order.
+// PF: the next chunk's fragments are loaded into registers one chunk ahead
+// (without PF they are read where they are used, which saves 6 NTC
+// registers and suits fragments in LDS).
 // ---------------------------------------------------------------------------
-template <int R, int TM, int NTC, int AM, int BLDS>
+template <int R, int TM, int NTC, int AM, int BLDS, int PF>
 __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
                                           const float* __restrict__ Bsrc, float* __restrict__ C,
                                           const GemmGeom& g, int wave, int lane, int ct0) {
@@ -273,8 +276,9 @@ __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
   if (blk >= nblk) return;  // no barrier follows
   int64_t rb[TM];
   block_rows(blk, rb);
-  float bq[2][NTC][6];
-  if (R >= 2) load_b(bq[0], 0);
+  constexpr bool kPre = PF && R >= 2;
+  float bq[kPre ? 2 : 1][NTC][6];
+  if (kPre) load_b(bq[0], 0);
   f32x4 buf[R][TM];
   int64_t kh = 0;
 #pragma unroll
@@ -306,7 +310,7 @@ __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         float b[NTC][6];
-        if (R >= 2) {
+        if constexpr (kPre) {
           const int nk = (kc + i + 1) & (g.KC - 1);
 #pragma unroll
           for (int n = 0; n < NTC; ++n)
@@ -370,7 +374,7 @@ __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
   }
 }
 
-template <int TM, int NTC, int AM, int BLDS>
+template <int TM, int NTC, int AM, int BLDS, int PF>
 __global__ __launch_bounds__(256) void stem_cgemm_f32g_kernel(Operand Ao, Operand Bo, Operand Co,
                                                               uint64_t s0, GemmGeom g) {
   extern __shared__ __align__(16) float sB[];
@@ -394,11 +398,11 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32g_kernel(Operand Ao, Operan
   }
   const float* Bsrc = BLDS ? (const float*)sB : Bf;
   if (g.KC >= 4)
-    f32g_rows<4, TM, NTC, AM, BLDS>(A, Bsrc, C, g, wave, lane, ct0);
+    f32g_rows<4, TM, NTC, AM, BLDS, PF>(A, Bsrc, C, g, wave, lane, ct0);
   else if (g.KC == 2)
-    f32g_rows<2, TM, NTC, AM, BLDS>(A, Bsrc, C, g, wave, lane, ct0);
+    f32g_rows<2, TM, NTC, AM, BLDS, PF>(A, Bsrc, C, g, wave, lane, ct0);
   else
-    f32g_rows<1, TM, NTC, AM, BLDS>(A, Bsrc, C, g, wave, lane, ct0);
+    f32g_rows<1, TM, NTC, AM, BLDS, PF>(A, Bsrc, C, g, wave, lane, ct0);
 }
 
 template <int TM, int NTC, int AM>
@@ -408,14 +412,21 @@ static void launch_f32g_t(const LaunchCtx& c) {
   const int gy = ntc_all / NTC;
   const int64_t want = std::max<int64_t>(1, c.sch.blocks / ((int64_t)gy * c.nz));
   const dim3 grid((unsigned)std::min<int64_t>(nblk, want), (unsigned)gy, (unsigned)c.nz);
+  // lds -1: fragments in LDS up to 64 KB, prefetched into registers;
+  // lds 1: in LDS up to the device limit, read where used; else global,
+  // prefetched
   const size_t lds = (size_t)c.g.KC * NTC * 384 * 4;
-  static size_t allowed = 0;
-  if (use_lds(c.sch.lds, lds) &&
-      allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1>, lds, &allowed) == hipSuccess)
-    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1>), grid, dim3(256), lds, c.st,
+  static size_t allowed_pf = 0, allowed_np = 0;
+  if (c.sch.lds == 1 && use_lds(1, lds) &&
+      allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0>, lds, &allowed_np) == hipSuccess)
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0>), grid, dim3(256), lds, c.st,
+                       *c.A, *c.B, *c.C, c.s0, c.g);
+  else if (c.sch.lds == -1 && use_lds(-1, lds) &&
+           allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1>, lds, &allowed_pf) == hipSuccess)
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1>), grid, dim3(256), lds, c.st,
                        *c.A, *c.B, *c.C, c.s0, c.g);
   else
-    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 0>), grid, dim3(256), 0, c.st,
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 0, 1>), grid, dim3(256), 0, c.st,
                        *c.A, *c.B, *c.C, c.s0, c.g);
 }
 
