@@ -441,7 +441,7 @@ std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
     const int top = std::min(4, ntc_all);
     for (int tm : {1, 2, 4}) {
       if (S.M % (64 * tm) != 0) continue;
-      for (int w : {top, top / 2}) {
+      for (int w : {top, top / 2, top / 4}) {
         if (w < 1 || tm * w > 4) continue;
         for (int blocks : {1024, 4096, 16384}) {
           // -1: LDS (up to 64 KB) with prefetch, else global with prefetch;
