@@ -421,6 +421,20 @@ def roofline(plan):
     }
 
 
+def cross_slice_kappa(plan, n_slices):
+    """How much the slices cancel: sum_s |T_s| / |sum_s T_s|, over the whole
+    amplitude vector (L2 norms) and per amplitude (median, max), from the
+    per-slice results.  The amplitude error scales with it."""
+    import torch
+
+    per = torch.stack([plan.contract(s, s + 1)[0] for s in range(n_slices)]).cpu().numpy()
+    tot = per.sum(axis=0)
+    vec = float(np.linalg.norm(per, axis=1).sum() / np.linalg.norm(tot))
+    amp = np.abs(per).sum(axis=0) / np.maximum(np.abs(tot), 1e-300)
+    return {"vector": round(vec, 3), "amplitude_median": round(float(np.median(amp)), 3),
+            "amplitude_max": round(float(amp.max()), 3)}
+
+
 def cpu_baseline(net, sample_slices, flops_per_slice):
     """The FP64 oracle, as it stands, on a few slices (host cores)."""
     from oracle import stemnet
@@ -561,6 +575,7 @@ def main():
                 worst = max(worst, stats.rel_l2(got, refs[s]))
             errs[precision] = worst
         line["amp_rel_l2_vs_oracle"] = errs
+        line["cross_slice_kappa"] = cross_slice_kappa(plans["fp32"], summ["n_slices"])
     for p in plans.values():
         p.close()
     torch.cuda.empty_cache()

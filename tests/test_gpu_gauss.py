@@ -5,8 +5,9 @@ Random stem networks whose steps have whole 3M tiles (K a multiple of 8,
 N of 16, M of 64) run with every such step forced to the 3M kernel in
 several launch schedules (row blocks per wave, column tiles, workgroups,
 branch fragments in LDS or not); every slice matches the oracle at
-relative L2 <= 1e-5 and the real-embedding result closely.  Forcing the
-3M product where it does not apply is refused.
+relative L2 <= 1e-5 and the real-embedding result closely, also on
+batched steps of hyperedge networks.  Forcing the 3M product where it
+does not apply is refused.
 """
 import numpy as np
 import pytest
@@ -76,6 +77,29 @@ def test_3m_product_matches_oracle(cfg):
         tot = plan.contract(proj=projs).cpu().numpy()
         for p in projs:
             assert stats.rel_l2(tot[p], base[p]) <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("seed", [60, 66])
+def test_3m_on_batched_steps_matches_oracle(seed):
+    """Hyperedge networks whose batched steps (kept shared labels) have whole
+    3M tiles: each batch index runs its own 3M product."""
+    net = random_stem_network(seed, stem_rank=14, n_steps=6, s_range=(3, 6), f_range=(4, 6),
+                              n_sliced=1, n_proj=1, n_open_final=6, batch_prob=0.5,
+                              rank_bounds=(8, 18))
+    onet = _c128(net)
+    plan = Plan(net)
+    steps = plan.steps()
+    elig = [i for i, s in enumerate(steps) if _eligible(s)]
+    assert any(steps[i]["n_batch"] > 0 for i in elig)
+    for tm, ntw, blocks, lds in SCHEDULES[:2]:
+        print(f"network seed {seed}: 3M on steps {elig}, tm {tm} ntw {ntw} lds {lds}", flush=True)
+        for i in elig:
+            plan.set_schedule(i, tm, ntw, blocks, lds, algo=1)
+        got = plan.contract(0, 2, proj=[0, 1]).cpu().numpy()
+        for p in (0, 1):
+            ref = stemnet.sliced_sum(onet, proj=p).reshape(-1)
+            assert stats.rel_l2(got[p], ref) <= 1e-5, p
     plan.close()
 
 
