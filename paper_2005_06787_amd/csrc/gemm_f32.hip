@@ -237,9 +237,10 @@ static void launch_f32_m(const LaunchCtx& c) {
 // only: M a multiple of 64 TM, K of 8, N of 16, output in block order.
 // PF: the next chunk's fragments are loaded into registers one chunk ahead
 // (without PF they are read where they are used, which saves 6 NTC
-// registers and suits fragments in LDS).
+// registers and suits fragments in LDS).  WAVES: waves per workgroup (4, or
+// 8 so that two waves per SIMD share one LDS copy of large fragments).
 // ---------------------------------------------------------------------------
-template <int R, int TM, int NTC, int AM, int BLDS, int PF>
+template <int R, int TM, int NTC, int AM, int BLDS, int PF, int WAVES>
 __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
                                           const float* __restrict__ Bsrc, float* __restrict__ C,
                                           const GemmGeom& g, int wave, int lane, int ct0) {
@@ -249,11 +250,11 @@ __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
   const int64_t kl0 = k_offset(2 * grp, g);
   const int64_t kl1 = k_offset(2 * grp + 1, g);
   const int64_t khmask = k_offset(g.K - 1, g) & ~k_offset(7, g);
-  const int64_t nblk = g.M / (64 * TM);
+  const int64_t nblk = g.M / (16 * WAVES * TM);
   const int ntc_all = g.NT >> 1;
 
   auto block_rows = [&](int64_t blk, int64_t (&rb)[TM]) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t row0 = (blk * WAVES + wave) * (16 * TM);
 #pragma unroll
     for (int t = 0; t < TM; ++t) rb[t] = row_hi((row0 >> 4) + t, g) | rlo;
   };
@@ -287,7 +288,7 @@ __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
     load_chunk(buf[i], rb, i, kh);
   }
   while (true) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t row0 = (blk * WAVES + wave) * (16 * TM);
     const int64_t nxt = blk + gridDim.x;
     const bool has_next = nxt < nblk;
     int64_t rbn[TM];
@@ -374,8 +375,8 @@ __device__ __forceinline__ void f32g_rows(const float* __restrict__ A,
   }
 }
 
-template <int TM, int NTC, int AM, int BLDS, int PF>
-__global__ __launch_bounds__(256) void stem_cgemm_f32g_kernel(Operand Ao, Operand Bo, Operand Co,
+template <int TM, int NTC, int AM, int BLDS, int PF, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void stem_cgemm_f32g_kernel(Operand Ao, Operand Bo, Operand Co,
                                                               uint64_t s0, GemmGeom g) {
   extern __shared__ __align__(16) float sB[];
   const int z = blockIdx.z;
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32g_kernel(Operand Ao, Operan
   const int ntc_all = g.NT >> 1;
   if (BLDS) {
     const int per_kc = NTC * 384;
-    for (int i = threadIdx.x * 4; i < g.KC * per_kc; i += 1024) {
+    for (int i = threadIdx.x * 4; i < g.KC * per_kc; i += 256 * WAVES) {
       const int kc = i / per_kc, r = i - kc * per_kc;
       *(f32x4*)(sB + kc * per_kc + r) = *(const f32x4*)(Bf + (size_t)(kc * ntc_all + ct0) * 384 + r);
     }
@@ -398,36 +399,42 @@ __global__ __launch_bounds__(256) void stem_cgemm_f32g_kernel(Operand Ao, Operan
   }
   const float* Bsrc = BLDS ? (const float*)sB : Bf;
   if (g.KC >= 4)
-    f32g_rows<4, TM, NTC, AM, BLDS, PF>(A, Bsrc, C, g, wave, lane, ct0);
+    f32g_rows<4, TM, NTC, AM, BLDS, PF, WAVES>(A, Bsrc, C, g, wave, lane, ct0);
   else if (g.KC == 2)
-    f32g_rows<2, TM, NTC, AM, BLDS, PF>(A, Bsrc, C, g, wave, lane, ct0);
+    f32g_rows<2, TM, NTC, AM, BLDS, PF, WAVES>(A, Bsrc, C, g, wave, lane, ct0);
   else
-    f32g_rows<1, TM, NTC, AM, BLDS, PF>(A, Bsrc, C, g, wave, lane, ct0);
+    f32g_rows<1, TM, NTC, AM, BLDS, PF, WAVES>(A, Bsrc, C, g, wave, lane, ct0);
 }
 
 template <int TM, int NTC, int AM>
 static void launch_f32g_t(const LaunchCtx& c) {
   const int ntc_all = c.g.NT >> 1;
-  const int64_t nblk = c.g.M / (64 * TM);
   const int gy = ntc_all / NTC;
   const int64_t want = std::max<int64_t>(1, c.sch.blocks / ((int64_t)gy * c.nz));
-  const dim3 grid((unsigned)std::min<int64_t>(nblk, want), (unsigned)gy, (unsigned)c.nz);
+  auto grid = [&](int waves) {
+    const int64_t nblk = c.g.M / (16 * waves * TM);
+    return dim3((unsigned)std::min<int64_t>(nblk, want), (unsigned)gy, (unsigned)c.nz);
+  };
   // lds -1: fragments in LDS up to 64 KB, prefetched into registers;
-  // lds 1: in LDS up to the device limit, read where used; else global,
-  // prefetched
+  // lds 1: in LDS up to the device limit, read where used; lds 2: as 1
+  // with 8-wave workgroups; else global, prefetched
   const size_t lds = (size_t)c.g.KC * NTC * 384 * 4;
-  static size_t allowed_pf = 0, allowed_np = 0;
-  if (c.sch.lds == 1 && use_lds(1, lds) &&
-      allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0>, lds, &allowed_np) == hipSuccess)
-    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0>), grid, dim3(256), lds, c.st,
-                       *c.A, *c.B, *c.C, c.s0, c.g);
+  static size_t allowed_pf = 0, allowed_np = 0, allowed_w8 = 0;
+  if (c.sch.lds == 2 && c.g.M % (128 * TM) == 0 && use_lds(1, lds) &&
+      allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0, 8>, lds, &allowed_w8) == hipSuccess)
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0, 8>), grid(8), dim3(512), lds,
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+  else if (c.sch.lds >= 1 && use_lds(1, lds) &&
+           allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0, 4>, lds, &allowed_np) == hipSuccess)
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0, 4>), grid(4), dim3(256), lds,
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else if (c.sch.lds == -1 && use_lds(-1, lds) &&
-           allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1>, lds, &allowed_pf) == hipSuccess)
-    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1>), grid, dim3(256), lds, c.st,
-                       *c.A, *c.B, *c.C, c.s0, c.g);
+           allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1, 4>, lds, &allowed_pf) == hipSuccess)
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1, 4>), grid(4), dim3(256), lds,
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else
-    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 0, 1>), grid, dim3(256), 0, c.st,
-                       *c.A, *c.B, *c.C, c.s0, c.g);
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 0, 1, 4>), grid(4), dim3(256), 0,
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
 }
 
 template <int AM>
