@@ -468,9 +468,12 @@ std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
     for (int w : ntws)
       for (int blocks : {1024, 4096, 16384}) {
         const size_t lds = precision == STEM_FP32 ? (size_t)kc * w * 1024 : (size_t)kc * w * 2048;
-        for (int l : {-1, 0, 1}) {
+        for (int l : {-1, 0, 1, 2}) {
           if (l == 0 && lds > (size_t)kLdsBudget) continue;  // -1 is already global
-          if (l == 1 && (lds <= (size_t)kLdsBudget || lds > lds_limit())) continue;
+          if (l >= 1 && (lds <= (size_t)kLdsBudget || lds > lds_limit())) continue;
+          // 2: split products with 8-wave workgroups sharing the LDS copy
+          if (l == 2 && (precision == STEM_FP32 || S.gemm.cmode != 1 || S.M % (128 * tm) != 0))
+            continue;
           GemmSched s;
           s.tm = tm;
           s.ntw = w;
@@ -492,7 +495,7 @@ stem_status stem_step_sched_set(stem_plan_t p, int32_t step, int32_t tm, int32_t
   if (step < 0 || step >= (int32_t)p->L.steps.size()) return fail(STEM_ERANGE, "step index");
   if ((tm != 1 && tm != 2 && tm != 4) || (ntw != 1 && ntw != 2 && ntw != 4 && ntw != 8) ||
       blocks < 256 || blocks > 65536 || lds < -1 || lds > 2 || algo < 0 || algo > 1 ||
-      (algo == 1 && ntw > 4) || (algo == 0 && lds == 2))
+      (algo == 1 && ntw > 4) || (algo == 0 && lds == 2 && p->precision == STEM_FP32))
     return fail(STEM_ERANGE, "schedule value outside its set");
   StepLayout& S = p->L.steps[step];
   if (algo == 1 && (p->precision != STEM_FP32 || S.gemm.cmode != 1 || S.K % 8 != 0 ||

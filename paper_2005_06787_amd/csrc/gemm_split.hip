@@ -55,7 +55,7 @@ struct SplitT<1> {
 // chunk's MFMAs its buffer is refilled with the chunk R places later (from
 // the next row block at the end of the current one; the last row block
 // re-reads its own rows), so R - 1 chunks are in flight.
-template <int R, int TM, int NTW, int BF16, int AM, int CM, int BLDS, int FULL>
+template <int R, int TM, int NTW, int BF16, int AM, int CM, int BLDS, int FULL, int WAVES>
 __device__ __forceinline__ void split_rows(const float* __restrict__ A,
                                            const uint16_t* __restrict__ Bh,
                                            const uint16_t* __restrict__ Bl, float inv_b,
@@ -72,11 +72,11 @@ __device__ __forceinline__ void split_rows(const float* __restrict__ A,
 #pragma unroll
   for (int i = 0; i < 4; ++i) kl[i] = k_offset(4 * grp + i, g);
   const int64_t khmask = k_offset(g.K - 1, g) & ~k_offset(15, g);
-  const int64_t rows_per_wg = 4 * 16 * TM;
+  const int64_t rows_per_wg = WAVES * 16 * TM;
   const int64_t nblk = (g.M + rows_per_wg - 1) / rows_per_wg;
 
   auto block_rows = [&](int64_t blk, int64_t (&rb)[TM]) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t row0 = (blk * WAVES + wave) * (16 * TM);
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
       const int64_t hi = row_hi((row0 >> 4) + t, g);  // wave-uniform
@@ -93,7 +93,7 @@ __device__ __forceinline__ void split_rows(const float* __restrict__ A,
   };
 
   int64_t blk = blockIdx.x;
-  if ((blk * 4 + wave) * (16 * TM) >= g.M) return;  // no barrier follows
+  if ((blk * WAVES + wave) * (16 * TM) >= g.M) return;  // no barrier follows
   int64_t rb[TM];
   block_rows(blk, rb);
   f32x4 buf[R][TM][2];
@@ -104,9 +104,9 @@ __device__ __forceinline__ void split_rows(const float* __restrict__ A,
     load_chunk(buf[i], rb, i, kh);
   }
   while (true) {
-    const int64_t row0 = (blk * 4 + wave) * (16 * TM);
+    const int64_t row0 = (blk * WAVES + wave) * (16 * TM);
     const int64_t nxt = blk + gridDim.x;
-    const bool has_next = nxt < nblk && (FULL || (nxt * 4 + wave) * (16 * TM) < g.M);
+    const bool has_next = nxt < nblk && (FULL || (nxt * WAVES + wave) * (16 * TM) < g.M);
     int64_t rbn[TM];
     if (has_next)
       block_rows(nxt, rbn);
@@ -214,8 +214,8 @@ __device__ __forceinline__ void split_rows(const float* __restrict__ A,
   }
 }
 
-template <int TM, int NTW, int BF16, int AM, int CM, int BLDS, int FULL>
-__global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Operand Bo,
+template <int TM, int NTW, int BF16, int AM, int CM, int BLDS, int FULL, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void stem_cgemm_split_kernel(Operand Ao, Operand Bo,
                                                                Operand Co, uint64_t s0,
                                                                GemmGeom g) {
   extern __shared__ __align__(16) uint16_t sBh[];
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
 
   if (BLDS) {
     const int per_kc = ntw * 512;  // halves of one part per k chunk
-    for (int i = threadIdx.x * 8; i < g.KC * per_kc; i += 2048) {
+    for (int i = threadIdx.x * 8; i < g.KC * per_kc; i += 512 * WAVES) {
       const int kc = i / per_kc, r = i - kc * per_kc;
       const size_t src = (size_t)(kc * g.NT + nt0) * 512 + r;
       *(u16x8*)(sBh + kc * NTW * 512 + r) = *(const u16x8*)(Bh + src);
@@ -250,29 +250,42 @@ __global__ __launch_bounds__(256) void stem_cgemm_split_kernel(Operand Ao, Opera
   // row (one for the small partial shapes that run without FULL)
   if constexpr (FULL) {
     if (g.KC >= 2)
-      split_rows<2, TM, NTW, BF16, AM, CM, BLDS, FULL>(A, Bhs, Bls, inv_b, C, g, wave, lane, nt0,
-                                                       ntw);
+      split_rows<2, TM, NTW, BF16, AM, CM, BLDS, FULL, WAVES>(A, Bhs, Bls, inv_b, C, g, wave,
+                                                              lane, nt0, ntw);
     else
-      split_rows<1, TM, NTW, BF16, AM, CM, BLDS, FULL>(A, Bhs, Bls, inv_b, C, g, wave, lane, nt0,
-                                                       ntw);
+      split_rows<1, TM, NTW, BF16, AM, CM, BLDS, FULL, WAVES>(A, Bhs, Bls, inv_b, C, g, wave,
+                                                              lane, nt0, ntw);
   } else {
-    split_rows<1, TM, NTW, BF16, AM, CM, BLDS, FULL>(A, Bhs, Bls, inv_b, C, g, wave, lane, nt0,
-                                                     ntw);
+    split_rows<1, TM, NTW, BF16, AM, CM, BLDS, FULL, WAVES>(A, Bhs, Bls, inv_b, C, g, wave, lane,
+                                                            nt0, ntw);
   }
 }
 
 template <int TM, int NTW, int BF16, int AM, int CM, int FULL>
 static void launch_split_f(const LaunchCtx& c, const dim3& grid) {
   const size_t lds = (size_t)c.g.KC * NTW * 512 * 2 * 2;
-  static size_t allowed = 0;
-  if (use_lds(c.sch.lds, lds) &&
-      allow_lds(stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1, FULL>, lds, &allowed) ==
+  static size_t allowed = 0, allowed_w8 = 0;
+  if constexpr (FULL) {
+    // lds 2: fragments in LDS shared by 8-wave workgroups (two waves per SIMD)
+    if (c.sch.lds == 2 && c.g.M % (128 * TM) == 0 && use_lds(1, lds) &&
+        allow_lds(stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1, FULL, 8>, lds, &allowed_w8) ==
+            hipSuccess) {
+      const int64_t nblk = c.g.M / (128 * TM);
+      const dim3 g8((unsigned)std::max<int64_t>(1, std::min<int64_t>(nblk, (grid.x + 1) / 2)),
+                    grid.y, grid.z);
+      hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1, FULL, 8>), g8,
+                         dim3(512), lds, c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+      return;
+    }
+  }
+  if (use_lds(c.sch.lds == 2 ? 1 : c.sch.lds, lds) &&
+      allow_lds(stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1, FULL, 4>, lds, &allowed) ==
           hipSuccess)
-    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1, FULL>), grid, dim3(256),
-                       lds, c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 1, FULL, 4>), grid,
+                       dim3(256), lds, c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else
-    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 0, FULL>), grid, dim3(256),
-                       0, c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+    hipLaunchKernelGGL((stem_cgemm_split_kernel<TM, NTW, BF16, AM, CM, 0, FULL, 4>), grid,
+                       dim3(256), 0, c.st, *c.A, *c.B, *c.C, c.s0, c.g);
 }
 
 // Whole shapes run the requested schedule without predicates; partial ones
