@@ -97,6 +97,33 @@ def test_error_codes():
     assert b"null" in C.lib().stem_last_error()
 
 
+def test_null_handles_are_refused_on_the_host():
+    """Entry points that take a plan or join handle refuse null before any
+    device work (no GPU needed)."""
+    lib = C.lib()
+    h = ctypes.c_void_p()
+    n = ctypes.c_uint64()
+    assert lib.stem_step_sched_set(None, 0, 1, 1, 4096, -1, 0) == C.STEM_EINVAL
+    assert lib.stem_join_create(None, None, 0, None, ctypes.byref(h)) == C.STEM_EINVAL
+    assert h.value is None
+    assert lib.stem_join_create(None, None, 0, None, None) == C.STEM_EINVAL
+    assert lib.stem_join_workspace_bytes(None, 1, ctypes.byref(n)) == C.STEM_EINVAL
+    assert lib.stem_join_contract(None, 0, 1, None, 1, None, 0, None, 0, None) == C.STEM_EINVAL
+    assert lib.stem_join_destroy(None) == C.STEM_OK
+
+
+def test_sliced_label_in_no_tensor_is_accepted():
+    """A sliced or projected label need not occur in the plan's tensors (the
+    two halves of a join list the same ones); the step shapes are unchanged."""
+    net = _tiny()
+    base = stem_plan_validate(net)
+    more = dict(net, sliced_labels=list(net.get("sliced_labels", [])) + [99],
+                proj_labels=list(net.get("proj_labels", [])) + [98])
+    s = stem_plan_validate(more)
+    assert s["n_slices"] == 2 * base["n_slices"]
+    assert s["flops_per_slice"] == base["flops_per_slice"]
+
+
 def test_hyperedge_steps_are_batched():
     """Label 1 joins three tensors: step 0 keeps it (a batched product over
     its 2 values), step 2 sums it."""
