@@ -674,7 +674,10 @@ static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   if (dev != p->device) return fail(STEM_EINVAL, "plan was created on another device");
-  if (!(flags & STEM_ACCUMULATE)) {
+  // without STEM_ACCUMULATE the first group of each batch entry overwrites
+  // its output, so out is only zeroed for an empty range
+  const bool fresh = !(flags & STEM_ACCUMULATE);
+  if (fresh && s0 == s1) {
     hipError_t e = launch_zero_f64(out, 2 * n_out * n_batch, st);
     if (e != hipSuccess) return fail(STEM_EHIP, std::string("zero: ") + hipGetErrorString(e));
   }
@@ -705,7 +708,13 @@ static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
       stem_status rs = run_chain(p, stem_op, bsel, c0, nz, wsb, half, ybase, time_this, st, &cur,
                                  &cur_buf);
       if (rs != STEM_OK) return rs;
-      hipError_t e = launch_acc_f64(cur, c0, nz, out + 2 * n_out * b, L.final_map, st);
+      // large results take the tiled sum (contiguous reads and writes)
+      hipError_t e =
+          L.final_labels.size() >= (size_t)kPermTileMaxBits
+              ? launch_acc_tiled(cur, c0, nz, out + 2 * n_out * b, L.final_perm, st,
+                                 fresh && c0 == s0)
+              : launch_acc_f64(cur, c0, nz, out + 2 * n_out * b, L.final_map, st,
+                               fresh && c0 == s0);
       if (e != hipSuccess) return fail(STEM_EHIP, std::string("accumulate: ") + hipGetErrorString(e));
     }
   }

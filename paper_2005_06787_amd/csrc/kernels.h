@@ -50,9 +50,14 @@ hipError_t launch_permute(const Operand& in, const Operand& out, const PermArgs&
 hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const Operand& C,
                         uint64_t s0, int nz, int64_t M, int64_t K, int64_t N,
                         const GemmLayout& lay, const GemmSched& sched, hipStream_t st);
-// out[o] += sum over z < nz (in order) of in_z[i], o = i re-ordered by m.
+// out[o] += sum over z < nz (in order) of in_z[i], o = i re-ordered by m
+// (overwrite: out[o] = that sum, out is not read).
 hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, const BitMap& m,
-                          hipStream_t st);
+                          hipStream_t st, bool overwrite = false);
+// The same sum with the reorder p (from the stem's final order to the
+// result's), staged through LDS in tiles; same bits as launch_acc_f64.
+hipError_t launch_acc_tiled(const Operand& in, uint64_t s0, int nz, double* out,
+                            const PermArgs& p, hipStream_t st, bool overwrite);
 hipError_t launch_zero_f64(double* p, uint64_t n, hipStream_t st);
 // Root join of two stem halves, split over K: for every slice z < nz and
 // chunk c of 2^chunk_log k values, part[(z * nchunks + c) * 2^(a+b) + o]

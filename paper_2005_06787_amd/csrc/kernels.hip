@@ -42,21 +42,31 @@ __global__ __launch_bounds__(256) void stem_permute_kernel(Operand in_op, Operan
     ob |= bit << p.nout[i];
   }
   const int T = 1 << p.t;
-  for (int e = threadIdx.x; e < T; e += blockDim.x) {
+  if (p.t == 0) {  // rank 0: one entry
+    if (threadIdx.x == 0) out[ob] = in[ib];
+    return;
+  }
+  // address bit 0 is tile bit 0 on both sides (the fastest bits are tile
+  // bits), so each thread moves two adjacent entries as one 16-byte access
+  for (int e = 2 * threadIdx.x; e < T; e += 2 * blockDim.x) {
     uint64_t a = ib;
-    for (int i = 0; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
-    tile[e + (e >> 5)] = in[a];
+    for (int i = 1; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
+    const float4 v = *(const float4*)(in + a);
+    tile[e + (e >> 5)] = make_float2(v.x, v.y);
+    tile[e + 1 + (e >> 5)] = make_float2(v.z, v.w);
   }
   __syncthreads();
-  for (int f = threadIdx.x; f < T; f += blockDim.x) {
+  for (int f = 2 * threadIdx.x; f < T; f += 2 * blockDim.x) {
     uint64_t a = ob;
     int e = 0;
-    for (int i = 0; i < p.t; ++i) {
+    for (int i = 1; i < p.t; ++i) {
       const int bit = (f >> i) & 1;
       a |= (uint64_t)bit << p.tout[i];
       e |= bit << p.f2e[i];
     }
-    out[a] = tile[e + (e >> 5)];
+    const int e1 = e | (1 << p.f2e[0]);
+    const float2 u = tile[e + (e >> 5)], w = tile[e1 + (e1 >> 5)];
+    *(float4*)(out + a) = make_float4(u.x, u.y, w.x, w.y);
   }
 }
 
@@ -213,12 +223,14 @@ hipError_t launch_cgemm(int precision, const Operand& A, const Operand& B, const
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void stem_acc_f64_kernel(Operand in_op, uint64_t s0, int nz,
                                                            double2* __restrict__ out, BitMap m,
-                                                           uint64_t n) {
+                                                           uint64_t n, int overwrite) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint64_t o = 0;
   for (int q = 0; q < m.rank; ++q) o |= ((i >> q) & 1ull) << m.dst[q];
-  double2 r = out[o];
+  // overwrite: start from 0 instead of reading out (0 + x is exact, so the
+  // bits equal zeroing out first)
+  double2 r = overwrite ? make_double2(0.0, 0.0) : out[o];
   for (int z = 0; z < nz; ++z) {
     const float2 v = ((const float2*)op_base(in_op, z, s0))[i];
     r.x += (double)v.x;
@@ -228,11 +240,74 @@ __global__ __launch_bounds__(256) void stem_acc_f64_kernel(Operand in_op, uint64
 }
 
 hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, const BitMap& m,
-                          hipStream_t st) {
+                          hipStream_t st, bool overwrite) {
   const uint64_t n = 1ull << m.rank;
   const uint64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(stem_acc_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, in, s0, nz,
-                     (double2*)out, m, n);
+                     (double2*)out, m, n, overwrite ? 1 : 0);
+  return hipGetLastError();
+}
+
+// The same sum for large results, staged through LDS like the permute so
+// that the slices' reads and the result's reads and writes are contiguous
+// runs: a workgroup loads its tile of the result (output order) into LDS,
+// adds every slice's entries (input order) in slice order, and writes the
+// tile back.  Per entry the additions are those of stem_acc_f64_kernel, in
+// the same order, so the bits are the same.
+__global__ __launch_bounds__(256) void stem_acc_tiled_kernel(Operand in_op, uint64_t s0, int nz,
+                                                             double2* __restrict__ out,
+                                                             PermArgs p, int overwrite) {
+  __shared__ double2 tile[(1 << kPermTileMaxBits) + (1 << kPermTileMaxBits) / 32];
+  const uint64_t w = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+  uint64_t ib = 0, ob = 0;
+  for (int i = 0; i < p.nn; ++i) {
+    const uint64_t bit = (w >> i) & 1ull;
+    ib |= bit << p.nin[i];
+    ob |= bit << p.nout[i];
+  }
+  const int T = 1 << p.t;
+  for (int f = threadIdx.x; f < T; f += blockDim.x) {
+    uint64_t a = ob;
+    int e = 0;
+    for (int i = 0; i < p.t; ++i) {
+      const int bit = (f >> i) & 1;
+      a |= (uint64_t)bit << p.tout[i];
+      e |= bit << p.f2e[i];
+    }
+    tile[e + (e >> 5)] = overwrite ? make_double2(0.0, 0.0) : out[a];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < T; e += blockDim.x) {
+    uint64_t a = ib;
+    for (int i = 0; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
+    double2 r = tile[e + (e >> 5)];
+    for (int z = 0; z < nz; ++z) {
+      const float2 v = ((const float2*)op_base(in_op, z, s0))[a];
+      r.x += (double)v.x;
+      r.y += (double)v.y;
+    }
+    tile[e + (e >> 5)] = r;
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < T; f += blockDim.x) {
+    uint64_t a = ob;
+    int e = 0;
+    for (int i = 0; i < p.t; ++i) {
+      const int bit = (f >> i) & 1;
+      a |= (uint64_t)bit << p.tout[i];
+      e |= bit << p.f2e[i];
+    }
+    out[a] = tile[e + (e >> 5)];
+  }
+}
+
+hipError_t launch_acc_tiled(const Operand& in, uint64_t s0, int nz, double* out,
+                            const PermArgs& p, hipStream_t st, bool overwrite) {
+  const uint64_t blocks = 1ull << p.nn;
+  const uint64_t gx = std::min<uint64_t>(blocks, 1ull << 20);
+  const uint64_t gy = blocks / gx;
+  hipLaunchKernelGGL(stem_acc_tiled_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st,
+                     in, s0, nz, (double2*)out, p, overwrite ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -478,6 +478,7 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     while (L->open[k] != cur[j]) ++k;
     L->final_map.dst[pos_in] = r - 1 - k;
   }
+  L->final_perm = make_perm(cur, L->open);
   S.n_steps = d->n_branches;
   S.peak_rank = L->peak_rank;
   S.n_open = d->n_open;

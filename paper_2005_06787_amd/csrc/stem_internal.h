@@ -153,6 +153,7 @@ struct PlanLayout {
   std::vector<StepLayout> steps;
   std::vector<int32_t> final_labels;
   BitMap final_map{};
+  PermArgs final_perm{};                 // the same reorder as tiles (large results)
   int32_t peak_rank = 0;       // over every stem the steps read or write
   int32_t max_ws_rank = 0;     // largest tensor written to the workspace
   int32_t max_rank = kDefaultMaxRank;
