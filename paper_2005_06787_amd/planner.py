@@ -448,7 +448,7 @@ class CircuitProblem:
 
 
 def scheme_network(pb: CircuitProblem, order, sliced, *, init_rank: int = 12,
-                   max_branch_rank: int = 12, merge: str = "dp", with_data: bool = True,
+                   max_branch_rank: int = 14, merge: str = "dp", with_data: bool = True,
                    stats: dict | None = None, step_cost=None) -> dict:
     """The stem network of a scheme (order, sliced labels) of a problem.
 
@@ -551,7 +551,7 @@ def two_sided_networks(pb: CircuitProblem, order, sliced, h: int, **kw):
 
 def plan_circuit(circuit: dict, open_qubits=(), closed_bits=None, proj_qubits=(), *,
                  n_sliced=None, max_width=None, trials: int = 64, seed: int = 0,
-                 init_rank: int = 12, max_branch_rank: int = 12, merge: str = "dp",
+                 init_rank: int = 12, max_branch_rank: int = 14, merge: str = "dp",
                  step_cost=None, local_window: int = 0) -> dict:
     """Sliced stem network of a circuit's amplitudes.
 

@@ -10,7 +10,8 @@ and the ranking of candidate slicing sets by the runtime models.
 * Candidate schemes: slicing sets of the chosen order from the randomised
   greedy slicer, and 32 other stem orders (seeded trials of the linear
   stem search, sliced greedily).  The analytic and MLP models predict
-  every candidate's total time (per-slice time x 2^|E_s|, paper §A.1); six
+  every candidate's total time (per-slice time x 2^|E_s|, paper §A.1; the
+  candidates' branches merged up to 12 labels); six
   candidates spread over the analytic ranking
   are measured (slice 0, tuned schedules), both models must order them like
   the measurements (Spearman rank correlation), and the MLP, trained on the
@@ -34,6 +35,7 @@ from paper_2005_06787_amd import _capi as C  # noqa: E402
 from paper_2005_06787_amd import runtime_model as rm  # noqa: E402
 
 CFG = configs.C5_53Q_M20
+MBR = 12   # merge bound of the ranked candidate plans (the MLP's training shapes)
 
 
 @pytest.fixture(scope="module")
@@ -123,7 +125,7 @@ def test_runtime_models_rank_candidate_slicings(scheme, tmp_path):
                                       max_width=CFG["max_width"], forbid=pb.forbid)
     cands, shapes, analytic = [], [], []
     for o, c in [(order, c) for c in sets] + others:
-        net_c = planner.scheme_network(pb, o, c, with_data=False)
+        net_c = planner.scheme_network(pb, o, c, with_data=False, max_branch_rank=MBR)
         try:   # schemes the library cannot hold (too many sliced labels on a tensor) drop out
             t = rm.scheme_seconds(net_c, "fp32", 1)["analytic_total_s"]
         except C.StemError:
@@ -135,7 +137,7 @@ def test_runtime_models_rank_candidate_slicings(scheme, tmp_path):
     assert len(cands) > len(sets)
 
     # measured step times of the scheme itself train the MLP
-    base = Plan(net)
+    base = Plan(planner.scheme_network(pb, order, sliced, max_branch_rank=MBR))
     base.tune(slices_in_flight=1, reps=1, cache_path=log)
     base.close()
     x, us = rm.read_tune_log(log)
@@ -146,7 +148,7 @@ def test_runtime_models_rank_candidate_slicings(scheme, tmp_path):
     picks = [int(ranked[int(round(q * (len(ranked) - 1)))]) for q in np.linspace(0, 1, 6)]
     measured = []
     for j in picks:
-        plan = Plan(planner.scheme_network(pb, cands[j][0], cands[j][1]))
+        plan = Plan(planner.scheme_network(pb, cands[j][0], cands[j][1], max_branch_rank=MBR))
         plan.tune(slices_in_flight=1, reps=1, cache_path=log)
         plan.contract(0, 1)
         torch.cuda.synchronize()

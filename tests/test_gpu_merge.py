@@ -48,15 +48,15 @@ def test_cost_model_merge_points_beat_greedy(tmp_path):
     pb = planner.CircuitProblem(circ, oq, closed)
     order, sliced, _, _ = planner.find_scheme(pb.tlabels, 64, 0, n_sliced=CFG["n_sliced"],
                                               forbid=pb.forbid)
-    greedy = planner.scheme_network(pb, order, sliced, merge="greedy")
-    dp = planner.scheme_network(pb, order, sliced, merge="dp")
-    none = planner.scheme_network(pb, order, sliced, merge="none")
+    greedy = planner.scheme_network(pb, order, sliced, merge="greedy", max_branch_rank=12)
+    dp = planner.scheme_network(pb, order, sliced, merge="dp", max_branch_rank=12)
+    none = planner.scheme_network(pb, order, sliced, merge="none", max_branch_rank=12)
     t_g, a_g, n_g, g = _measure(greedy, log)
     t_d, a_d, n_d, _ = _measure(dp, log)
     t_n, a_n, n_n, _ = _measure(none, log)
     x, us = rm.read_tune_log(log)
     model = rm.fit(x, us, steps=3000, lr=3e-3, seed=0)
-    learned = planner.scheme_network(pb, order, sliced, merge="dp",
+    learned = planner.scheme_network(pb, order, sliced, merge="dp", max_branch_rank=12,
                                      step_cost=rm.mlp_step_cost(model, "fp32", g))
     model.close()
     t_m, a_m, n_m, _ = _measure(learned, log)
