@@ -557,7 +557,17 @@ stem_status stem_tune(stem_plan_t p, uint32_t nz, void* ws, uint64_t ws_bytes, i
     // successive launches swap the two stem buffers, so that every launch
     // reads what the one before it wrote, as the steps of a contraction do
     // (values are irrelevant to the timing)
-    const Operand a_in[2] = {batched(in, h, S.hpos_a), batched(out, h, S.hpos_a)};
+    // the first step reads the initial stem, which can be larger than the
+    // workspace buffers (they hold the tensors the steps write); its timing
+    // launches read the stem's first variant, as slice 0 does
+    const bool from_stem = i == 0 && !S.permuted;
+    const Operand stem0 = plain_operand(p->d_stem, 0);
+    if (!from_stem && (8ull << S.rank_in) > (uint64_t)half) {
+      rs = fail(STEM_EINVAL, "tuning: step input larger than its workspace buffer");
+      break;
+    }
+    const Operand a_in[2] = {batched(from_stem ? stem0 : in, h, S.hpos_a),
+                             batched(from_stem ? stem0 : out, h, S.hpos_a)};
     const Operand c_out[2] = {batched(out, h, cpos), batched(in, h, cpos)};
     TuneBest win;
     for (const GemmSched& c : candidates(S, p->precision)) {

@@ -3,7 +3,8 @@ and the ranking of candidate slicing sets by the runtime models.
 
 * Slice 0 of the width-30 scheme, step by step at its real shapes (stem up
   to 2^30): every step runs on its own from the GPU's input of that step,
-  and 2048 sampled output entries are checked against the oracle's row
+  with the autotuner's schedule (as the benchmark runs it), and 2048
+  sampled output entries are checked against the oracle's row
   formula on the same input (the local error of each step); the last
   step's 64 values equal the whole plan's slice 0.  FP32 and split FP16,
   bound 1e-5 relative L2 per step.
@@ -58,8 +59,9 @@ def _fix(labels, data, sliced):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_fp16"])
-def test_slice0_full_width_local_error_per_step(scheme, precision):
+def test_slice0_full_width_local_error_per_step(scheme, precision, tmp_path):
     _, _, sliced, net = scheme
+    cache = str(tmp_path / "tune.txt")
     sl = set(sliced)
     whole = Plan(net, precision=precision)
     ref_final = whole.contract(0, 1).cpu().numpy()[0]
@@ -81,6 +83,7 @@ def test_slice0_full_width_local_error_per_step(scheme, precision):
         one = {"open_labels": out_labels, "sliced_labels": step_sliced, "proj_labels": [],
                "stem": {"labels": labels}, "branches": [br]}
         plan = Plan(one, precision=precision, stem_device=x)
+        plan.tune(slices_in_flight=1, reps=1, cache_path=cache)
         y64 = plan.contract(0, 1)[0]
         plan.close()
         y = y64.to(torch.complex64)
