@@ -47,19 +47,31 @@ __global__ __launch_bounds__(256) void stem_permute_kernel(Operand in_op, Operan
     return;
   }
   // address bit 0 is tile bit 0 on both sides (the fastest bits are tile
-  // bits), so each thread moves two adjacent entries as one 16-byte access
-  for (int e = 2 * threadIdx.x; e < T; e += 2 * blockDim.x) {
-    uint64_t a = ib;
-    for (int i = 1; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
+  // bits), so each thread moves two adjacent entries as one 16-byte access.
+  // Thread x takes tile entries 2x + 512 j: tile bits 1..8 are fixed per
+  // thread (their address parts are computed once), bits 9.. follow j.
+  const int e0 = 2 * (int)threadIdx.x;
+  const int lb = p.t < 9 ? p.t : 9;
+  uint64_t in_lo = 0, out_lo = 0;
+  int e_lo = 0;
+  for (int i = 1; i < lb; ++i) {
+    const int bit = (e0 >> i) & 1;
+    in_lo |= (uint64_t)bit << p.tin[i];
+    out_lo |= (uint64_t)bit << p.tout[i];
+    e_lo |= bit << p.f2e[i];
+  }
+  for (int e = e0; e < T; e += 512) {
+    uint64_t a = ib | in_lo;
+    for (int i = 9; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
     const float4 v = *(const float4*)(in + a);
     tile[e + (e >> 5)] = make_float2(v.x, v.y);
     tile[e + 1 + (e >> 5)] = make_float2(v.z, v.w);
   }
   __syncthreads();
-  for (int f = 2 * threadIdx.x; f < T; f += 2 * blockDim.x) {
-    uint64_t a = ob;
-    int e = 0;
-    for (int i = 1; i < p.t; ++i) {
+  for (int f = e0; f < T; f += 512) {
+    uint64_t a = ob | out_lo;
+    int e = e_lo;
+    for (int i = 9; i < p.t; ++i) {
       const int bit = (f >> i) & 1;
       a |= (uint64_t)bit << p.tout[i];
       e |= bit << p.f2e[i];
@@ -266,20 +278,39 @@ __global__ __launch_bounds__(256) void stem_acc_tiled_kernel(Operand in_op, uint
     ob |= bit << p.nout[i];
   }
   const int T = 1 << p.t;
-  for (int f = threadIdx.x; f < T; f += blockDim.x) {
-    uint64_t a = ob;
-    int e = 0;
-    for (int i = 0; i < p.t; ++i) {
+  // thread x takes tile entries x + 256 j: tile bits 0..7 are fixed per
+  // thread (their address parts are computed once), bits 8.. follow j
+  const int x0 = (int)threadIdx.x;
+  const int lb = p.t < 8 ? p.t : 8;
+  uint64_t in_lo = 0, out_lo = 0;
+  int e_lo = 0;
+  for (int i = 0; i < lb; ++i) {
+    const int bit = (x0 >> i) & 1;
+    in_lo |= (uint64_t)bit << p.tin[i];
+    out_lo |= (uint64_t)bit << p.tout[i];
+    e_lo |= bit << p.f2e[i];
+  }
+  auto out_entry = [&](int f, uint64_t* a_out, int* e_out) {
+    uint64_t a = ob | out_lo;
+    int e = e_lo;
+    for (int i = 8; i < p.t; ++i) {
       const int bit = (f >> i) & 1;
       a |= (uint64_t)bit << p.tout[i];
       e |= bit << p.f2e[i];
     }
+    *a_out = a;
+    *e_out = e;
+  };
+  for (int f = x0; f < T; f += 256) {
+    uint64_t a;
+    int e;
+    out_entry(f, &a, &e);
     tile[e + (e >> 5)] = overwrite ? make_double2(0.0, 0.0) : out[a];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < T; e += blockDim.x) {
-    uint64_t a = ib;
-    for (int i = 0; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
+  for (int e = x0; e < T; e += 256) {
+    uint64_t a = ib | in_lo;
+    for (int i = 8; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
     double2 r = tile[e + (e >> 5)];
     for (int z = 0; z < nz; ++z) {
       const float2 v = ((const float2*)op_base(in_op, z, s0))[a];
@@ -289,14 +320,10 @@ __global__ __launch_bounds__(256) void stem_acc_tiled_kernel(Operand in_op, uint
     tile[e + (e >> 5)] = r;
   }
   __syncthreads();
-  for (int f = threadIdx.x; f < T; f += blockDim.x) {
-    uint64_t a = ob;
-    int e = 0;
-    for (int i = 0; i < p.t; ++i) {
-      const int bit = (f >> i) & 1;
-      a |= (uint64_t)bit << p.tout[i];
-      e |= bit << p.f2e[i];
-    }
+  for (int f = x0; f < T; f += 256) {
+    uint64_t a;
+    int e;
+    out_entry(f, &a, &e);
     out[a] = tile[e + (e >> 5)];
   }
 }
