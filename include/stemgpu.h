@@ -125,7 +125,8 @@ typedef struct stem_step_info {
                              sched_algo 1, -1 and 0 also load the next k chunk's fragments
                              into registers ahead, 1 reads them from LDS where used; 2 (algo
                              1 or a split precision) is 1 with 8-wave workgroups, two waves
-                             per SIMD sharing the copy */
+                             per SIMD sharing the copy; 3 (algo 1) keeps them in LDS up to
+                             160 KB, loads them ahead, 8-wave workgroups */
   float tuned_us;         /* stem_tune's time of that schedule per launch, or -1 */
   int32_t tuned_slices;   /* slices per launch stem_tune measured with */
   int32_t n_batch;        /* labels the stem and the branch share and keep (a later branch
@@ -253,8 +254,8 @@ stem_status stem_batch_destroy(stem_batch_t batch);
  * §A.3 on the GPU efficiency of small products): tm row blocks per wave (1,
  * 2, 4), ntw column tiles per workgroup (1, 2, 4, 8; with algo 1: 1, 2, 4
  * tiles of 16 complex columns), blocks target workgroups (256 .. 65536),
- * lds (-1, 0, 1, and 2 with algo 1 or a split precision, as sched_lds),
- * algo (0 or 1, as sched_algo).  Values the
+ * lds (-1, 0, 1; 2 with algo 1 or a split precision; 3 with algo 1; as
+ * sched_lds), algo (0 or 1, as sched_algo).  Values the
  * step's shape cannot use are clamped the way the kernels clamp them
  * (read back with stem_step_info_get).  STEM_ERANGE for values outside
  * those sets; STEM_EUNSUPPORTED for algo 1 on a split-precision plan or a

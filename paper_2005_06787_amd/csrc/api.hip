@@ -446,12 +446,13 @@ std::vector<GemmSched> candidates(const StepLayout& S, int precision) {
         for (int blocks : {1024, 4096, 16384}) {
           // -1: LDS (up to 64 KB) with prefetch, else global with prefetch;
           // 0: global with prefetch; 1: LDS up to the device limit, no
-          // prefetch; 2: as 1 with 8-wave workgroups (above 64 KB)
+          // prefetch; 2: as 1 with 8-wave workgroups, 3: LDS with prefetch
+          // and 8-wave workgroups (2 and 3 above 64 KB)
           const size_t lds = (size_t)kc * w * 1536;
-          for (int l : {-1, 0, 1, 2}) {
+          for (int l : {-1, 0, 1, 2, 3}) {
             if (l == 0 && lds > (size_t)kLdsBudget) continue;
             if (l >= 1 && lds > lds_limit()) continue;
-            if (l == 2 && (lds <= (size_t)kLdsBudget || S.M % (128 * tm) != 0)) continue;
+            if (l >= 2 && (lds <= (size_t)kLdsBudget || S.M % (128 * tm) != 0)) continue;
             GemmSched s;
             s.tm = tm;
             s.ntw = w;
@@ -494,8 +495,9 @@ stem_status stem_step_sched_set(stem_plan_t p, int32_t step, int32_t tm, int32_t
   if (!p) return fail(STEM_EINVAL, "null plan");
   if (step < 0 || step >= (int32_t)p->L.steps.size()) return fail(STEM_ERANGE, "step index");
   if ((tm != 1 && tm != 2 && tm != 4) || (ntw != 1 && ntw != 2 && ntw != 4 && ntw != 8) ||
-      blocks < 256 || blocks > 65536 || lds < -1 || lds > 2 || algo < 0 || algo > 1 ||
-      (algo == 1 && ntw > 4) || (algo == 0 && lds == 2 && p->precision == STEM_FP32))
+      blocks < 256 || blocks > 65536 || lds < -1 || lds > 3 || algo < 0 || algo > 1 ||
+      (algo == 1 && ntw > 4) || (algo == 0 && lds >= 2 && p->precision == STEM_FP32) ||
+      (algo == 0 && lds == 3))
     return fail(STEM_ERANGE, "schedule value outside its set");
   StepLayout& S = p->L.steps[step];
   if (algo == 1 && (p->precision != STEM_FP32 || S.gemm.cmode != 1 || S.K % 8 != 0 ||

@@ -417,11 +417,17 @@ static void launch_f32g_t(const LaunchCtx& c) {
   };
   // lds -1: fragments in LDS up to 64 KB, prefetched into registers;
   // lds 1: in LDS up to the device limit, read where used; lds 2: as 1
-  // with 8-wave workgroups; else global, prefetched
+  // with 8-wave workgroups; lds 3: in LDS up to the device limit,
+  // prefetched, 8-wave workgroups; else global, prefetched
   const size_t lds = (size_t)c.g.KC * NTC * 384 * 4;
-  static size_t allowed_pf = 0, allowed_np = 0, allowed_w8 = 0;
-  if (c.sch.lds == 2 && c.g.M % (128 * TM) == 0 && use_lds(1, lds) &&
-      allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0, 8>, lds, &allowed_w8) == hipSuccess)
+  static size_t allowed_pf = 0, allowed_np = 0, allowed_w8 = 0, allowed_w8pf = 0;
+  const bool w8 = c.g.M % (128 * TM) == 0 && use_lds(1, lds);
+  if (c.sch.lds == 3 && w8 &&
+      allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1, 8>, lds, &allowed_w8pf) == hipSuccess)
+    hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 1, 8>), grid(8), dim3(512), lds,
+                       c.st, *c.A, *c.B, *c.C, c.s0, c.g);
+  else if (c.sch.lds == 2 && w8 &&
+           allow_lds(stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0, 8>, lds, &allowed_w8) == hipSuccess)
     hipLaunchKernelGGL((stem_cgemm_f32g_kernel<TM, NTC, AM, 1, 0, 8>), grid(8), dim3(512), lds,
                        c.st, *c.A, *c.B, *c.C, c.s0, c.g);
   else if (c.sch.lds >= 1 && use_lds(1, lds) &&

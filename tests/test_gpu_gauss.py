@@ -28,7 +28,7 @@ NETS = [
     (53, 12, 8, (3, 4), (4, 5), 2, 1, None),
 ]
 SCHEDULES = [(1, 1, 1024, -1), (1, 4, 4096, 1), (2, 2, 16384, 0), (4, 1, 4096, -1),
-             (1, 4, 4096, 2), (2, 2, 1024, 2)]
+             (1, 4, 4096, 2), (2, 2, 1024, 2), (1, 4, 4096, 3)]
 
 
 def _net(cfg):

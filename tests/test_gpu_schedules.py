@@ -48,14 +48,15 @@ def test_eight_wave_workgroups_give_the_same_bits(seed, precision, algo):
     print(f"network seed {seed} {precision}: steps {use}", flush=True)
     n = 1 << plan.n_sliced
     outs = []
-    for lds in (1, 2):
+    for lds in ((1, 2, 3) if algo == 1 else (1, 2)):
         for i in use:
             info = plan.set_schedule(i, 2, 2, 4096, lds, algo)
             assert info["sched_lds"] == lds
         outs.append(plan.contract(0, n, proj=[0, 1]).clone())
-    assert torch.equal(outs[0], outs[1])
+    for o in outs[1:]:
+        assert torch.equal(outs[0], o)
     onet = _c128(net)
-    got = outs[1].cpu().numpy()
+    got = outs[-1].cpu().numpy()
     for p in (0, 1):
         ref = stemnet.sliced_sum(onet, proj=p).reshape(-1)
         assert stats.rel_l2(got[p], ref) <= TOL[precision], p
