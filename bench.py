@@ -328,6 +328,44 @@ def two_sided_30q(steps: int, tune_cache=None):
     return out
 
 
+def merged14_30q(steps: int, tune_cache=None):
+    """The headline circuit, order and sliced labels with branches merged up
+    to 14 labels (the planner's default) instead of the 12 that keep every
+    branch within 2^12 entries: fewer, larger products that move fewer
+    bytes per slice."""
+    import torch
+
+    from paper_2005_06787_amd import Plan, planner
+    from workloads import configs
+
+    cfg = configs.CIRCUIT_CONFIGS["c2_5x6_m14"]
+    circ, oq, closed = configs.circuit_case(cfg)
+    net = planner.plan_circuit(circ, oq, closed, n_sliced=cfg["n_sliced"], trials=64, seed=0,
+                               max_branch_rank=14)
+    out = {"workload": "5x6 grid, 14 cycles, 30 qubits, 2^10 slices, branches merged up to "
+                       "2^14 entries"}
+    for precision in ("fp32", "split_fp16"):
+        plan = Plan(net, precision=precision)
+        summ = plan.summary()
+        n = int(summ["n_slices"])
+        plan.tune(slices_in_flight=plan.default_slices_in_flight(n), reps=2, cache_path=tune_cache)
+        res = plan.contract(0, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.contract(0, n, out=res)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[precision] = {"ms_per_step": round(dt * 1e3, 3), "slices_per_s": round(n / dt, 1),
+                          "tflops": round(summ["flops_per_slice"] * n / dt / 1e12, 2)}
+        log(f"30-qubit plan merged to 2^14 {precision}: {n / dt:.0f} slices/s")
+        plan.close()
+    out.update({"peak_rank": summ["peak_rank"], "n_steps": summ["n_steps"],
+                "flops_per_slice": summ["flops_per_slice"],
+                "bytes_per_slice": summ["bytes_per_slice"]})
+    return out
+
+
 def sampling_30q(n_prefixes: int, tune_cache=None):
     """Frugal rejection sampling on the 30-qubit, 14-cycle circuit: random
     prefixes of the 24 closed qubits as projected batch entries (64
@@ -364,6 +402,41 @@ def sampling_30q(n_prefixes: int, tune_cache=None):
             "samples_per_s": round(res["n_samples"] / dt, 2),
             "acceptance": round(res["acceptance"], 4), "samples": res["n_samples"],
             "xeb_of_samples": round(res["xeb"], 4)}
+
+
+def real_embedding_rate(plan, tune_log, steps, warmup, n_slices, stream):
+    """The FP32 headline with every product computed as the real embedding
+    (four real products per complex one) instead of the tuner's 3M choices:
+    each such step takes its fastest real-embedding schedule from the
+    tuning log.  Run after the headline numbers; the plan keeps these
+    schedules."""
+    best = {}
+    with open(tune_log) as f:
+        for ln in f:
+            p = ln.split()
+            if len(p) != 14 or p[0] != "stem-tune-v2" or p[12] != "0":
+                continue
+            key = tuple(int(x) for x in p[1:8])
+            us = float(p[13])
+            if key not in best or us < best[key][0]:
+                best[key] = (us, [int(x) for x in p[8:12]])
+    g = plan.default_slices_in_flight(n_slices)
+    changed = 0
+    for i, st in enumerate(plan.steps()):
+        if st["sched_algo"] != 1:
+            continue
+        key = (0, st["amode"], st["cmode"], int(st["M"]).bit_length() - 1,
+               int(st["K"]).bit_length() - 1, int(st["N"]).bit_length() - 1, g << st["n_batch"])
+        if key not in best:
+            return None
+        tm, ntw, blocks, lds = best[key][1]
+        plan.set_schedule(i, tm, ntw, blocks, lds, 0)
+        changed += 1
+    dt, _ = timed_run(plan, steps, warmup, n_slices, stream)
+    ms = dt / steps * 1e3
+    flops = plan.summary()["flops_per_slice"] * n_slices
+    return {"ms_per_step": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 4),
+            "slices_per_s": round(n_slices / (ms * 1e-3), 2), "steps_changed": changed}
 
 
 def timed_run(plan, steps, warmup, n_slices, stream):
@@ -488,6 +561,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
         return
+    if args.tune_cache is None:
+        # the tuner's measurement log, also read back for the real-embedding rate
+        import tempfile
+
+        args.tune_cache = os.path.join(tempfile.mkdtemp(prefix="stem_tune_"), "tune.txt")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "layout is a design, not a measured path", file=sys.stderr)
@@ -547,7 +625,8 @@ def main():
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": "5x6 grid, 14 cycles, 30 qubits, 6 open (64 amplitudes), "
-                               "2^10 slices, FP32 complex products",
+                               "2^10 slices, branches of 2^4-2^12 entries, FP32 complex "
+                               "products",
                    "n_slices": summ["n_slices"], "n_steps": summ["n_steps"],
                    "peak_rank": summ["peak_rank"], "n_permutes": summ["n_permutes"],
                    "parallelism": "1 GPU"},
@@ -576,6 +655,11 @@ def main():
             errs[precision] = worst
         line["amp_rel_l2_vs_oracle"] = errs
         line["cross_slice_kappa"] = cross_slice_kappa(plans["fp32"], summ["n_slices"])
+    if not args.no_tune:
+        re_ = real_embedding_rate(plans["fp32"], args.tune_cache, args.steps, args.warmup,
+                                  summ["n_slices"], stream)
+        if re_ is not None:
+            line["fp32_real_embedding"] = re_
     for p in plans.values():
         p.close()
     torch.cuda.empty_cache()
@@ -585,6 +669,7 @@ def main():
         line["slice_53q_m20"] = slice_53q(3, args.tune_cache)
         line["sampling_30q"] = sampling_30q(8, args.tune_cache)
         line["locally_optimised_30q"] = locally_optimised_30q(3, args.tune_cache)
+        line["merged14_30q"] = merged14_30q(3, args.tune_cache)
         line["two_sided_30q"] = two_sided_30q(3, args.tune_cache)
     print(json.dumps(line), flush=True)
 

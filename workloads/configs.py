@@ -18,7 +18,7 @@ CIRCUIT_CONFIGS = {
                       n_sliced=0, bitstring_seed=1001, sample_seed=2001),
     "c2_5x6_m14": dict(rows=5, cols=6, cycles=14, seed=2, dead=(),
                        open_rows=range(0, 2), open_cols=range(3, 6), prefix_seed=1002,
-                       n_sliced=10, slice_sample_seed=2002, max_branch_rank=14),
+                       n_sliced=10, slice_sample_seed=2002, max_branch_rank=12),
 }
 
 # 53 qubits (6x9 grid without site (0, 4)), 20 cycles: one slice at the
