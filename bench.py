@@ -545,7 +545,7 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-FP16 run")
     ap.add_argument("--no-tune", action="store_true", help="default launch schedules")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the isolated-stem and batched-circuit workloads")
+                    help="skip the comparison runs (FP32 real embedding) and the other workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy and exit (counter calibration)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache / measurement log")
@@ -655,7 +655,7 @@ def main():
             errs[precision] = worst
         line["amp_rel_l2_vs_oracle"] = errs
         line["cross_slice_kappa"] = cross_slice_kappa(plans["fp32"], summ["n_slices"])
-    if not args.no_tune:
+    if not args.no_tune and not args.no_extra:
         re_ = real_embedding_rate(plans["fp32"], args.tune_cache, args.steps, args.warmup,
                                   summ["n_slices"], stream)
         if re_ is not None:
