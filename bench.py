@@ -87,12 +87,12 @@ def batched_workload(steps: int, tune_cache=None):
     20-24), the first 512 slices of each, as one graph launch."""
     import torch
 
-    from paper_2005_06787_amd import Batch, Plan, planner
+    from paper_2005_06787_amd import Batch, Plan, ceilings, planner
     from workloads import configs, tensors
     from workloads.circuits import block_qubits, make_circuit
 
     cfg = configs.BATCH_5X8
-    plans, ranges, flops = [], [], 0.0
+    plans, ranges, flops, nbytes, ws_max = [], [], 0.0, 0.0, 0
     t0 = time.perf_counter()
     for j, (cyc, w) in enumerate(zip(cfg["cycles"], cfg["widths"])):
         circ = make_circuit(cfg["rows"], cfg["cols"], cyc, cfg["circuit_seed0"] + j)
@@ -107,6 +107,8 @@ def batched_workload(steps: int, tune_cache=None):
         plans.append(plan)
         ranges.append((0, n))
         flops += plan.summary()["flops_per_slice"] * n
+        nbytes += plan.summary()["bytes_per_slice"] * n
+        ws_max = max(ws_max, plan.workspace_bytes(group))
         log(f"batched circuit {j}: {cyc} cycles, width {net['stats']['peak_width']}, "
             f"{len(net['sliced_labels'])} sliced labels, group {group}")
     log(f"batched workload planned and tuned in {time.perf_counter() - t0:.1f} s")
@@ -124,10 +126,21 @@ def batched_workload(steps: int, tune_cache=None):
     out = {"workload": "8 circuits, 5x8 grid (40 qubits), 10-14 cycles, widths 20-24, "
                        "first 512 slices each, one graph launch, FP32",
            "slices": n_sl, "ms_per_launch": round(dt * 1e3, 3),
-           "slices_per_s": round(n_sl / dt, 1), "tflops": round(flops / dt / 1e12, 3)}
+           "slices_per_s": round(n_sl / dt, 1), "tflops": round(flops / dt / 1e12, 3),
+           "algorithmic_gbs": round(nbytes / dt / 1e9, 1)}
     batch.close()
     for p in plans:
         p.close()
+    torch.cuda.empty_cache()
+    # both copy ceilings: the stems of these circuits (2^20-2^24 entries) fit the
+    # 256 MiB last-level cache one at a time, but a plan's group of slices in
+    # flight does not (its workspace is the working set of one step)
+    hbm = ceilings.copy_gbs(4 << 30, 16)
+    llc = ceilings.copy_gbs(64 << 20, 16, reps=50)
+    out.update({"largest_group_workspace_gib": round(ws_max / 2**30, 2),
+                "hbm_copy_gbs": round(hbm, 1), "llc_copy_gbs_64mib": round(llc, 1),
+                "frac_of_hbm_copy": round(nbytes / dt / 1e9 / hbm, 3),
+                "frac_of_llc_copy": round(nbytes / dt / 1e9 / llc, 3)})
     return out
 
 
