@@ -656,7 +656,7 @@ def main():
     # amplitude error: sampled slices against the FP64 oracle (also the CPU baseline)
     if not args.no_cpu:
         rng = np.random.Generator(np.random.PCG64(cfg["slice_sample_seed"]))
-        sample = [int(s) for s in rng.choice(summ["n_slices"], size=16, replace=False)]
+        sample = [int(s) for s in rng.choice(summ["n_slices"], size=64, replace=False)]
         base, refs = cpu_baseline(net, sample, summ["flops_per_slice"])
         line["cpu_baseline"] = base
         errs = {}
