@@ -722,7 +722,7 @@ static stem_status contract_impl(stem_plan_t p, uint64_t s0, uint64_t s1,
       if (rs != STEM_OK) return rs;
       // large results take the tiled sum (contiguous reads and writes)
       hipError_t e =
-          L.final_labels.size() >= (size_t)kPermTileMaxBits
+          L.final_labels.size() >= (size_t)kAccTileMaxBits
               ? launch_acc_tiled(cur, c0, nz, out + 2 * n_out * b, L.final_perm, st,
                                  fresh && c0 == s0)
               : launch_acc_f64(cur, c0, nz, out + 2 * n_out * b, L.final_map, st,

@@ -269,7 +269,7 @@ hipError_t launch_acc_f64(const Operand& in, uint64_t s0, int nz, double* out, c
 __global__ __launch_bounds__(256) void stem_acc_tiled_kernel(Operand in_op, uint64_t s0, int nz,
                                                              double2* __restrict__ out,
                                                              PermArgs p, int overwrite) {
-  __shared__ double2 tile[(1 << kPermTileMaxBits) + (1 << kPermTileMaxBits) / 32];
+  __shared__ double2 tile[(1 << kAccTileMaxBits) + (1 << kAccTileMaxBits) / 32];
   const uint64_t w = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
   uint64_t ib = 0, ob = 0;
   for (int i = 0; i < p.nn; ++i) {

@@ -40,7 +40,8 @@ bool same_order(const std::vector<int32_t>& from, const std::vector<int32_t>& to
   return from == to;
 }
 
-PermArgs make_perm(const std::vector<int32_t>& from, const std::vector<int32_t>& to) {
+PermArgs make_perm(const std::vector<int32_t>& from, const std::vector<int32_t>& to, int low_bits,
+                   int max_bits) {
   PermArgs p;
   std::memset(&p, 0, sizeof(p));
   const int r = (int)from.size();
@@ -51,14 +52,14 @@ PermArgs make_perm(const std::vector<int32_t>& from, const std::vector<int32_t>&
   for (int j = 0; j < r; ++j) dst[r - 1 - j] = pos_out[from[j]];
   // tile: the fastest input bits and the input bits that become the fastest
   // output bits, then more fast input bits up to the tile size
-  const int low = std::min(kPermTileLowBits, r);
+  const int low = std::min(low_bits, r);
   std::vector<bool> in_tile(r, false);
   for (int q = 0; q < low; ++q) in_tile[q] = true;
   for (int q = 0; q < r; ++q)
     if (dst[q] < low) in_tile[q] = true;
   int t = 0;
   for (int q = 0; q < r; ++q) t += in_tile[q] ? 1 : 0;
-  const int target = std::min(r, kPermTileMaxBits);
+  const int target = std::min(r, max_bits);
   for (int q = 0; q < r && t < target; ++q)
     if (!in_tile[q]) {
       in_tile[q] = true;
@@ -478,7 +479,7 @@ stem_status build_layout(const stem_plan_desc* d, PlanLayout* L, std::string* er
     while (L->open[k] != cur[j]) ++k;
     L->final_map.dst[pos_in] = r - 1 - k;
   }
-  L->final_perm = make_perm(cur, L->open);
+  L->final_perm = make_perm(cur, L->open, kAccTileLowBits, kAccTileMaxBits);
   S.n_steps = d->n_branches;
   S.peak_rank = L->peak_rank;
   S.n_open = d->n_open;

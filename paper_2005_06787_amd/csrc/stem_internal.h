@@ -13,8 +13,11 @@
 namespace stem {
 
 constexpr int kDefaultMaxRank = 33;
-constexpr int kPermTileLowBits = 5;   // output and input runs of 32 entries (256 B)
-constexpr int kPermTileMaxBits = 10;  // at most 1024 entries per permute tile
+constexpr int kPermTileLowBits = 5;   // permute: output and input runs of 32 entries (256 B)
+constexpr int kPermTileMaxBits = 11;  // permute: at most 2048 entries per tile (measured
+                                      // faster than 1024 or 4096 on 2^17-2^30-entry stems)
+constexpr int kAccTileLowBits = 5;    // result sum: the same runs, FP64 tile entries
+constexpr int kAccTileMaxBits = 10;   // result sum: at most 1024 entries per tile
 
 // Bit permutation of a rank-r tensor, in the form the permute kernel takes.
 // Input address bit p (0 = least significant) moves to output bit dst[p].
@@ -165,8 +168,11 @@ struct PlanLayout {
 stem_status build_layout(const stem_plan_desc* d, PlanLayout* out, std::string* err);
 
 // Bit permutation that re-stores a tensor from C order over `from` to C
-// order over `to` (both permutations of one label set).
-PermArgs make_perm(const std::vector<int32_t>& from, const std::vector<int32_t>& to);
+// order over `to` (both permutations of one label set).  The LDS tile holds
+// the `low_bits` fastest input and output bits, padded with the next
+// fastest input bits up to `max_bits`.
+PermArgs make_perm(const std::vector<int32_t>& from, const std::vector<int32_t>& to,
+                   int low_bits = kPermTileLowBits, int max_bits = kPermTileMaxBits);
 
 // True when `from` and `to` are the same order.
 bool same_order(const std::vector<int32_t>& from, const std::vector<int32_t>& to);
