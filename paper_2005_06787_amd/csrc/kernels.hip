@@ -282,11 +282,10 @@ __global__ __launch_bounds__(256) void stem_acc_tiled_kernel(Operand in_op, uint
   // thread (their address parts are computed once), bits 8.. follow j
   const int x0 = (int)threadIdx.x;
   const int lb = p.t < 8 ? p.t : 8;
-  uint64_t in_lo = 0, out_lo = 0;
+  uint64_t out_lo = 0;
   int e_lo = 0;
   for (int i = 0; i < lb; ++i) {
     const int bit = (x0 >> i) & 1;
-    in_lo |= (uint64_t)bit << p.tin[i];
     out_lo |= (uint64_t)bit << p.tout[i];
     e_lo |= bit << p.f2e[i];
   }
@@ -308,16 +307,27 @@ __global__ __launch_bounds__(256) void stem_acc_tiled_kernel(Operand in_op, uint
     tile[e + (e >> 5)] = overwrite ? make_double2(0.0, 0.0) : out[a];
   }
   __syncthreads();
-  for (int e = x0; e < T; e += 256) {
-    uint64_t a = ib | in_lo;
-    for (int i = 8; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
-    double2 r = tile[e + (e >> 5)];
+  // the slices' entries in pairs: tile bit 0 is input address bit 0, so
+  // thread x reads tile entries 2x + 512 j and 2x + 1 + 512 j as one
+  // 16-byte load (tile bits 1..8 fixed per thread, bits 9.. follow j); the
+  // host runs this kernel on tiles of 2^10 entries only
+  const int lb2 = p.t < 9 ? p.t : 9;
+  uint64_t in_lo2 = 0;
+  for (int i = 1; i < lb2; ++i) in_lo2 |= (uint64_t)(((2 * x0) >> i) & 1) << p.tin[i];
+  for (int e = 2 * x0; e < T; e += 512) {
+    uint64_t a = ib | in_lo2;
+    for (int i = 9; i < p.t; ++i) a |= (uint64_t)((e >> i) & 1) << p.tin[i];
+    const int s = e + (e >> 5);  // e is even: entry e + 1 sits at s + 1
+    double2 r0 = tile[s], r1 = tile[s + 1];
     for (int z = 0; z < nz; ++z) {
-      const float2 v = ((const float2*)op_base(in_op, z, s0))[a];
-      r.x += (double)v.x;
-      r.y += (double)v.y;
+      const float4 v = *(const float4*)((const float2*)op_base(in_op, z, s0) + a);
+      r0.x += (double)v.x;
+      r0.y += (double)v.y;
+      r1.x += (double)v.z;
+      r1.y += (double)v.w;
     }
-    tile[e + (e >> 5)] = r;
+    tile[s] = r0;
+    tile[s + 1] = r1;
   }
   __syncthreads();
   for (int f = x0; f < T; f += 256) {
@@ -330,6 +340,8 @@ __global__ __launch_bounds__(256) void stem_acc_tiled_kernel(Operand in_op, uint
 
 hipError_t launch_acc_tiled(const Operand& in, uint64_t s0, int nz, double* out,
                             const PermArgs& p, hipStream_t st, bool overwrite) {
+  // the kernel reads entry pairs and owns 4 tile entries per thread
+  if (p.t < 1 || p.t > kAccTileMaxBits) return hipErrorInvalidValue;
   const uint64_t blocks = 1ull << p.nn;
   const uint64_t gx = std::min<uint64_t>(blocks, 1ull << 20);
   const uint64_t gy = blocks / gx;
