@@ -243,7 +243,21 @@ __global__ __launch_bounds__(256) void stem_acc_f64_kernel(Operand in_op, uint64
   // overwrite: start from 0 instead of reading out (0 + x is exact, so the
   // bits equal zeroing out first)
   double2 r = overwrite ? make_double2(0.0, 0.0) : out[o];
-  for (int z = 0; z < nz; ++z) {
+  // the loads of 16 slices are issued before they are added (in slice
+  // order), so that a short result is not one memory latency per slice
+  constexpr int kBatch = 16;
+  int z = 0;
+  for (; z + kBatch <= nz; z += kBatch) {
+    float2 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = ((const float2*)op_base(in_op, z + u, s0))[i];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      r.x += (double)v[u].x;
+      r.y += (double)v[u].y;
+    }
+  }
+  for (; z < nz; ++z) {
     const float2 v = ((const float2*)op_base(in_op, z, s0))[i];
     r.x += (double)v.x;
     r.y += (double)v.y;
